@@ -1,0 +1,179 @@
+"""Literal Python oracle for h-degrees and (k,h)-core numbers.
+
+TEST INFRASTRUCTURE ONLY: this module is the slow, obviously correct
+reference used by the tests, the smoke check and the benchmark's CPU
+baseline.  It shares no code with the GPU library.
+
+Written from Section II (definitions) and Section III (Algorithm 1) of the
+paper.  Graphs are given as (n, row_ptr, col) CSR arrays of a simple
+undirected graph; vertex sets as boolean/uint8 masks.
+"""
+from __future__ import annotations
+
+from collections import deque
+
+import numpy as np
+
+
+def _rows(n, row_ptr, col):
+    rp = [int(x) for x in row_ptr]
+    cl = [int(x) for x in col]
+    return [cl[rp[v]:rp[v + 1]] for v in range(n)]
+
+
+def h_neighbourhood(adj, alive, h, v):
+    """N_v^h(G(S)): vertices u != v in S with dis_{G(S)}(u, v) <= h.
+
+    Distances are shortest-path hop counts inside the subgraph induced by
+    S = {x : alive[x]} (Section II); dead vertices are never relays.
+    """
+    dist = {v: 0}
+    q = deque([v])
+    while q:
+        x = q.popleft()
+        if dist[x] == h:
+            continue
+        for y in adj[x]:
+            if alive[y] and y not in dist:
+                dist[y] = dist[x] + 1
+                q.append(y)
+    del dist[v]
+    return set(dist)
+
+
+def hdeg(n, row_ptr, col, alive, h):
+    """d_v^h(G(S)) for every v in S; 0 for vertices outside S."""
+    adj = _rows(n, row_ptr, col)
+    alive = [True] * n if alive is None else [bool(a) for a in alive]
+    return np.array([len(h_neighbourhood(adj, alive, h, v)) if alive[v] else 0
+                     for v in range(n)], dtype=np.int64)
+
+
+def brute_core(n, row_ptr, col, h):
+    """core_h(v) straight from Definition 2, by enumerating every vertex set.
+
+    core_h(v) = max over S containing v of min_{u in S} d_u^h(G(S)): every
+    S whose minimum h-degree is k lies inside the (k,h)-core, and the
+    (k,h)-core itself is such a set.  Exponential; n <= 12 only.
+    """
+    if n > 12:
+        raise ValueError("brute force is limited to n <= 12")
+    adj = _rows(n, row_ptr, col)
+    best = [0] * n
+    for mask in range(1, 1 << n):
+        alive = [(mask >> i) & 1 == 1 for i in range(n)]
+        members = [i for i in range(n) if alive[i]]
+        k = min(len(h_neighbourhood(adj, alive, h, u)) for u in members)
+        for u in members:
+            if k > best[u]:
+                best[u] = k
+    return np.array(best, dtype=np.int64)
+
+
+def alg1_peel(n, row_ptr, col, h):
+    """The basic peeling algorithm (Algorithm 1), one vertex at a time.
+
+    Buckets B[d] hold vertices by current h-degree; the level k runs upward
+    from 0 (a vertex with h-degree 0 gets core 0); the vertex picked from
+    B[k] is the smallest id (any choice gives the same result).  After a
+    removal every u in N_v^h(G) has its h-degree recomputed in G(V minus v)
+    and moves to bucket max(k, d).  Returns (core, removal order).
+    """
+    adj = _rows(n, row_ptr, col)
+    alive = [True] * n
+    d = [len(h_neighbourhood(adj, alive, h, v)) for v in range(n)]
+    buckets = [set() for _ in range(n + 1)]
+    for v in range(n):
+        buckets[d[v]].add(v)
+    core = [0] * n
+    order = []
+    for k in range(0, n + 1):
+        while buckets[k]:
+            v = min(buckets[k])
+            buckets[k].remove(v)
+            core[v] = k
+            order.append(v)
+            ball = h_neighbourhood(adj, alive, h, v)
+            alive[v] = False
+            for u in ball:
+                nd = len(h_neighbourhood(adj, alive, h, u))
+                buckets[d[u]].discard(u)
+                d[u] = max(k, nd)
+                buckets[d[u]].add(u)
+    return np.array(core, dtype=np.int64), order
+
+
+def bz_kcore(n, row_ptr, col):
+    """Classical core numbers (h = 1) by the linear bin-sort peeling.
+
+    Vertices are kept in an array sorted by current degree with bin start
+    positions; removing the minimum-degree vertex decrements each remaining
+    neighbour of larger degree and swaps it to the front of its bin.
+    """
+    adj = _rows(n, row_ptr, col)
+    deg = [len(a) for a in adj]
+    md = max(deg) if n else 0
+    bin_count = [0] * (md + 1)
+    for x in deg:
+        bin_count[x] += 1
+    start = [0] * (md + 1)
+    s = 0
+    for k in range(md + 1):
+        start[k] = s
+        s += bin_count[k]
+    pos = [0] * n
+    vert = [0] * n
+    nxt = list(start)
+    for v in range(n):
+        pos[v] = nxt[deg[v]]
+        vert[pos[v]] = v
+        nxt[deg[v]] += 1
+    for i in range(n):
+        v = vert[i]
+        for u in adj[v]:
+            if deg[u] > deg[v]:
+                du = deg[u]
+                pu = pos[u]
+                pw = start[du]
+                w = vert[pw]
+                if u != w:
+                    vert[pu], vert[pw] = w, u
+                    pos[u], pos[w] = pw, pu
+                start[du] += 1
+                deg[u] -= 1
+    return np.array(deg, dtype=np.int64)
+
+
+def level_sync_peel(n, row_ptr, col, h):
+    """Level-synchronous peeling with from-scratch recomputation.
+
+    Each round: k <- max(k, min alive d); P = alive vertices with d <= k all
+    get core k; the vertices within h hops of P in the graph before removal
+    (Observations 1-2, for a removed set) have their h-degree recomputed in
+    the graph after removal.  Returns (core, round, trace) with
+    trace = [(k, |P|, |A|) per round].
+    """
+    adj = _rows(n, row_ptr, col)
+    alive = [True] * n
+    d = [len(h_neighbourhood(adj, alive, h, v)) for v in range(n)]
+    core = [0] * n
+    rnd = [0] * n
+    trace = []
+    k, r, left = 0, 0, n
+    while left:
+        k = max(k, min(d[v] for v in range(n) if alive[v]))
+        P = [v for v in range(n) if alive[v] and d[v] <= k]
+        affected = set()
+        for p in P:
+            core[p], rnd[p] = k, r
+            affected |= h_neighbourhood(adj, alive, h, p)
+        affected -= set(P)
+        for p in P:
+            alive[p] = False
+        for u in affected:
+            d[u] = len(h_neighbourhood(adj, alive, h, u))
+        trace.append((k, len(P), len(affected)))
+        left -= len(P)
+        r += 1
+    return np.array(core, dtype=np.int64), np.array(rnd, dtype=np.int64), trace
+
