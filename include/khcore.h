@@ -1,0 +1,134 @@
+/*
+ * khcore.h -- C ABI of the MI355X (gfx950) h-degree / (k,h)-core library.
+ *
+ * The library computes h-hop degrees and distance-generalised core numbers
+ * of a simple undirected unweighted graph G = (V, E) (Section II of
+ * "Scaling Up Distance-generalized Core Decomposition", arXiv 2006.03372):
+ *
+ *   N_v^h(G(S)) = { u in S, u != v : dis_{G(S)}(u, v) <= h }   (S = live set)
+ *   d_v^h(G(S)) = |N_v^h(G(S))|                                 (h-degree)
+ *   core_h(v)   = largest k such that a (k,h)-core contains v   (Definition 2)
+ *
+ * Distances are hop counts inside the subgraph induced by the live
+ * vertices: dead vertices are neither counted nor used as relays.
+ *
+ * Conventions for every entry point
+ *   - Graph arrays, masks and outputs are DEVICE pointers (hipMalloc'd or
+ *     torch CUDA tensors); the caller owns them.  A graph handle keeps the
+ *     caller's CSR pointers (not copies): they must stay valid and
+ *     unchanged until khc_graph_destroy.
+ *   - Work runs on the stream given to khc_create (NULL: the null stream).
+ *   - Every call returns 0 on success or a negative KHC_E* code; the text
+ *     of the last error of a context is available from khc_last_error.
+ *     Nothing throws across this interface.
+ *   - One context per host thread; calls on one context must not overlap.
+ */
+#ifndef KHCORE_H
+#define KHCORE_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define KHC_OK 0
+#define KHC_EINVAL (-1) /* null pointer, h == 0, size mismatch, bad option */
+#define KHC_EGRAPH (-2) /* CSR is not a simple undirected graph            */
+#define KHC_ENOMEM (-3) /* device allocation failed or workspace cap hit   */
+#define KHC_EHIP (-4)   /* HIP runtime error (sticky for the context)      */
+#define KHC_ELIMIT (-5) /* round limit exceeded (internal consistency)     */
+
+typedef struct khc_ctx khc_ctx;
+typedef struct khc_graph khc_graph;
+
+/* Simple undirected graph in CSR form, device pointers.
+ *   n        number of vertices, n < 2^32 - 1
+ *   nnz      number of arcs = 2 |E| (row_ptr[n] must equal nnz)
+ *   row_ptr  uint64[n+1], row_ptr[0] == 0, non-decreasing
+ *   col      uint32[nnz], each row strictly increasing, no self-loops, and
+ *            arc u->v present iff arc v->u is present (Section II: an
+ *            undirected unweighted graph). */
+typedef struct {
+    uint32_t n;
+    uint64_t nnz;
+    const uint64_t *row_ptr;
+    const uint32_t *col;
+} khc_csr;
+
+/* Counters of one decomposition (host struct, filled on request). */
+typedef struct {
+    uint64_t rounds;          /* peeling rounds                                 */
+    uint64_t h_recomputes;    /* h-degrees recomputed by bounded BFS            */
+    uint64_t hm1_recomputes;  /* (h-1)-degrees recomputed (bounded schedule)    */
+    uint64_t bfs_batches;     /* multi-source BFS batches launched              */
+    uint64_t affected_total;  /* sum over rounds of the affected-set size       */
+    uint32_t max_level;       /* largest core number                            */
+    uint32_t width_words;     /* source-lane words per vertex of the last batch */
+    double wall_ms;           /* host wall time of the call                     */
+} khc_stats;
+
+/* ---- context ---------------------------------------------------------- */
+
+/* Create a context on HIP device `device` that enqueues all work on
+ * `hip_stream` (a hipStream_t; NULL = null stream). */
+int khc_create(khc_ctx **out, int device, void *hip_stream);
+int khc_destroy(khc_ctx *ctx);
+/* Message for the last failing call on ctx (static storage of the ctx). */
+const char *khc_last_error(const khc_ctx *ctx);
+
+/* Options (khc_set_option).  Values are validated; unknown ids: KHC_EINVAL. */
+#define KHC_OPT_MAX_WIDTH 1       /* max uint64 words per vertex per BFS batch (1..32, pow2; default 16) */
+#define KHC_OPT_SCHEDULE 2        /* 0 = plain recompute of the affected set, 1 = bounded (default)     */
+#define KHC_OPT_WORKSPACE_LIMIT 3 /* cap on workspace bytes (0 = none)                                  */
+#define KHC_OPT_VALIDATE 4        /* 1 = validate the CSR in khc_graph_create (default 1)               */
+#define KHC_OPT_WAVES_PER_CU 5    /* persistent workgroups per CU for BFS levels (1..16; default 4)     */
+int khc_set_option(khc_ctx *ctx, int option, int64_t value);
+
+/* ---- graph store ------------------------------------------------------ */
+
+/* Wrap a device CSR (Section II's G) and build the row schedule used by
+ * the BFS kernels (rows bucketed by degree).  With validation on, a graph
+ * that is not simple and undirected gives KHC_EGRAPH.  Synchronous. */
+int khc_graph_create(khc_ctx *ctx, const khc_csr *g, khc_graph **out);
+int khc_graph_destroy(khc_graph *g);
+
+/* Validate a CSR without keeping it: 0 or KHC_EGRAPH (message says why). */
+int khc_validate_csr(khc_ctx *ctx, const khc_csr *g);
+
+/* ---- h-degrees -------------------------------------------------------- */
+
+/* d_v^h(G(S)) for every vertex, S = { v : alive[v] != 0 } (alive == NULL:
+ * S = V).  Section II definition of the h-hop degree; the per-vertex
+ * computations are independent (Section IV-D runs them in parallel).
+ *   alive  device uint8[n] or NULL
+ *   h      >= 1
+ *   deg    device uint32[n] output; dead vertices get 0
+ * Asynchronous on the context stream. */
+int khdeg_compute(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                  uint32_t *deg);
+
+/* h-degrees of the listed live vertices only: deg[i] = d^h of verts[i].
+ *   verts  device uint32[count]; alive as above.  Asynchronous. */
+int khdeg_compute_list(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                       const uint32_t *verts, uint32_t count, uint32_t *deg);
+
+/* ---- (k,h)-core decomposition ----------------------------------------- */
+
+/* core_h(v) for every vertex (problem statement, Section II), by
+ * level-synchronous peeling: each round removes every live vertex whose
+ * h-degree is at most the level k = max(k, min live h-degree), gives it
+ * core k, and recomputes the h-degree of the live vertices within h hops
+ * of the removed ones (Algorithms 1-2, Observations 1-2).
+ *   core        device uint32[n] output (isolated vertices: 0)
+ *   peel_round  device uint32[n] output or NULL: round of removal
+ *   stats       host struct or NULL
+ * Synchronous (reads a few scalars per round). */
+int khcore_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,
+                     uint32_t *peel_round, khc_stats *stats);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KHCORE_H */

@@ -1,0 +1,410 @@
+// C ABI entry points: context, workspace, graph store and h-degrees.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <vector>
+
+#include "khc_internal.h"
+
+namespace khc {
+
+int set_error(khc_ctx *ctx, int code, const std::string &msg) {
+    if (ctx) ctx->err = msg;
+    return code;
+}
+
+int check_hip(khc_ctx *ctx, hipError_t e, const char *what) {
+    if (e == hipSuccess) return KHC_OK;
+    if (ctx) ctx->sticky = 1;
+    return set_error(ctx, KHC_EHIP, std::string(what) + ": " + hipGetErrorString(e));
+}
+
+int ws_get(khc_ctx *ctx, int slot, size_t bytes, void **out) {
+    if (bytes == 0) bytes = 8;
+    DevBuf &b = ctx->bufs[slot];
+    if (b.bytes >= bytes) {
+        *out = b.ptr;
+        return KHC_OK;
+    }
+    size_t want = bytes + bytes / 8;  // some headroom for growth
+    uint64_t total = ctx->ws_bytes - b.bytes + want;
+    if (ctx->ws_limit && total > ctx->ws_limit) {
+        want = bytes;
+        total = ctx->ws_bytes - b.bytes + want;
+        if (total > ctx->ws_limit)
+            return set_error(ctx, KHC_ENOMEM, "workspace limit exceeded (" + std::to_string(total) +
+                                                  " > " + std::to_string(ctx->ws_limit) + " bytes)");
+    }
+    if (b.ptr) {
+        hipError_t e = hipStreamSynchronize(ctx->stream);
+        if (e != hipSuccess) return check_hip(ctx, e, "stream sync before workspace growth");
+        (void)hipFree(b.ptr);
+        ctx->ws_bytes -= b.bytes;
+        b.ptr = nullptr;
+        b.bytes = 0;
+    }
+    void *p = nullptr;
+    hipError_t e = hipMalloc(&p, want);
+    if (e != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(ctx, KHC_ENOMEM, "hipMalloc of " + std::to_string(want) + " bytes failed");
+    }
+    // zero on allocation: kernels rely on some buffers starting cleared
+    e = hipMemsetAsync(p, 0, want, ctx->stream);
+    if (e != hipSuccess) return check_hip(ctx, e, "workspace clear");
+    b.ptr = p;
+    b.bytes = want;
+    ctx->ws_bytes += want;
+    *out = p;
+    return KHC_OK;
+}
+
+namespace {
+
+// Error bits of the CSR validator.
+enum : uint32_t {
+    VBAD_OFFSETS = 1,
+    VBAD_RANGE = 2,
+    VSELF_LOOP = 4,
+    VUNSORTED = 8,
+    VASYMMETRIC = 16,
+};
+
+__global__ void validate_rows_kernel(uint32_t n, uint64_t nnz, const uint64_t *row_ptr,
+                                     uint32_t *flags) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    if (v == 0 && (row_ptr[0] != 0 || row_ptr[n] != nnz)) atomicOr(flags, VBAD_OFFSETS);
+    if (v < n && row_ptr[v + 1] < row_ptr[v]) atomicOr(flags, VBAD_OFFSETS);
+}
+
+// One thread per arc: range, self-loop, strict order within the row, and
+// the reverse arc (binary search in the target row).
+__global__ void validate_arcs_kernel(uint32_t n, uint64_t nnz, const uint64_t *row_ptr,
+                                     const uint32_t *col, uint32_t *flags) {
+    const uint64_t e = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    if (e >= nnz) return;
+    // row of arc e: last v with row_ptr[v] <= e
+    uint32_t lo = 0, hi = n;
+    while (hi - lo > 1) {
+        uint32_t mid = lo + (hi - lo) / 2;
+        if (row_ptr[mid] <= e) lo = mid; else hi = mid;
+    }
+    const uint32_t v = lo;
+    const uint32_t u = col[e];
+    if (u >= n) {
+        atomicOr(flags, VBAD_RANGE);
+        return;
+    }
+    if (u == v) atomicOr(flags, VSELF_LOOP);
+    if (e > row_ptr[v] && col[e - 1] >= u) atomicOr(flags, VUNSORTED);
+    uint64_t a = row_ptr[u], b = row_ptr[u + 1];
+    bool found = false;
+    while (a < b) {
+        uint64_t mid = a + (b - a) / 2;
+        uint32_t c = col[mid];
+        if (c == v) { found = true; break; }
+        if (c < v) a = mid + 1; else b = mid;
+    }
+    if (!found) atomicOr(flags, VASYMMETRIC);
+}
+
+__global__ void fill_u32_kernel(uint32_t *p, uint32_t value, uint64_t count) {
+    for (uint64_t i = (uint64_t)blockIdx.x * blockDim.x + threadIdx.x; i < count;
+         i += (uint64_t)gridDim.x * blockDim.x)
+        p[i] = value;
+}
+
+// Append every live vertex that has a live neighbour (the others have
+// h-degree 0 and need no BFS).  Wave-aggregated atomic append.
+__global__ void compact_sources_kernel(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                                       const uint8_t *alive, uint32_t *out, uint32_t *count) {
+    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    bool keep = false;
+    if (v < n && (!alive || alive[v])) {
+        for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            if (!alive || alive[col[e]]) {
+                keep = true;
+                break;
+            }
+        }
+    }
+    const uint64_t m = __ballot(keep);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(m);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(count, (uint32_t)__builtin_popcountll(m));
+    base = __shfl(base, leader, 64);
+    if (keep) out[base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = v;
+}
+
+int grid_for(uint64_t count, int threads, int cap) {
+    uint64_t g = (count + threads - 1) / threads;
+    if (g < 1) g = 1;
+    if (g > (uint64_t)cap) g = cap;
+    return (int)g;
+}
+
+int check_csr_args(khc_ctx *ctx, const khc_csr *g) {
+    if (!g) return set_error(ctx, KHC_EINVAL, "csr is null");
+    if (g->n == 0xFFFFFFFFu) return set_error(ctx, KHC_EINVAL, "n must be below 2^32-1");
+    if (!g->row_ptr) return set_error(ctx, KHC_EINVAL, "row_ptr is null");
+    if (g->nnz > 0 && !g->col) return set_error(ctx, KHC_EINVAL, "col is null");
+    return KHC_OK;
+}
+
+int validate_impl(khc_ctx *ctx, const khc_csr *g) {
+    int rc = check_csr_args(ctx, g);
+    if (rc) return rc;
+    void *flags;
+    if ((rc = ws_get(ctx, WS_FLAGS, 64, &flags))) return rc;
+    uint32_t *f = (uint32_t *)flags;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, f, 0u, (uint64_t)1);
+    hipLaunchKernelGGL(validate_rows_kernel, dim3(grid_for((uint64_t)g->n + 1, 256, 1 << 20)),
+                       dim3(256), 0, st, g->n, g->nnz, g->row_ptr, f);
+    uint32_t host = 0;
+    hipError_t e = hipMemcpyAsync(&host, f, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(ctx, e, "validate rows");
+    if (!host && g->nnz) {
+        hipLaunchKernelGGL(validate_arcs_kernel, dim3((unsigned)((g->nnz + 255) / 256)), dim3(256), 0,
+                           st, g->n, g->nnz, g->row_ptr, g->col, f);
+        e = hipMemcpyAsync(&host, f, 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return check_hip(ctx, e, "validate arcs");
+    }
+    if (host) {
+        std::string m = "CSR is not a simple undirected graph:";
+        if (host & VBAD_OFFSETS) m += " bad row offsets (row_ptr[0] != 0, row_ptr[n] != nnz or decreasing);";
+        if (host & VBAD_RANGE) m += " column id >= n;";
+        if (host & VSELF_LOOP) m += " self-loop;";
+        if (host & VUNSORTED) m += " row not strictly increasing (unsorted or duplicate arc);";
+        if (host & VASYMMETRIC) m += " arc without its reverse;";
+        return set_error(ctx, KHC_EGRAPH, m);
+    }
+    return KHC_OK;
+}
+
+template <typename T>
+int upload(khc_ctx *ctx, const std::vector<T> &v, T **out) {
+    size_t bytes = std::max<size_t>(v.size() * sizeof(T), 8);
+    void *p = nullptr;
+    if (hipMalloc(&p, bytes) != hipSuccess) {
+        (void)hipGetLastError();
+        return set_error(ctx, KHC_ENOMEM, "hipMalloc for graph schedule failed");
+    }
+    if (!v.empty()) {
+        hipError_t e = hipMemcpy(p, v.data(), v.size() * sizeof(T), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(p);
+            return check_hip(ctx, e, "graph schedule upload");
+        }
+    }
+    *out = (T *)p;
+    return KHC_OK;
+}
+
+}  // namespace
+}  // namespace khc
+
+using namespace khc;
+
+extern "C" {
+
+int khc_create(khc_ctx **out, int device, void *hip_stream) {
+    if (!out) return KHC_EINVAL;
+    *out = nullptr;
+    int ndev = 0;
+    if (hipGetDeviceCount(&ndev) != hipSuccess || ndev == 0) {
+        (void)hipGetLastError();
+        return KHC_EHIP;
+    }
+    if (device < 0 || device >= ndev) return KHC_EINVAL;
+    if (hipSetDevice(device) != hipSuccess) return KHC_EHIP;
+    khc_ctx *c = new khc_ctx();
+    c->device = device;
+    c->stream = (hipStream_t)hip_stream;
+    c->bufs.resize(WS_NUM_SLOTS);
+    hipDeviceProp_t prop;
+    if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (hipHostMalloc((void **)&c->host_scalars, 256, hipHostMallocDefault) != hipSuccess) {
+        delete c;
+        return KHC_ENOMEM;
+    }
+    *out = c;
+    return KHC_OK;
+}
+
+int khc_destroy(khc_ctx *ctx) {
+    if (!ctx) return KHC_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    (void)hipStreamSynchronize(ctx->stream);
+    for (auto &b : ctx->bufs)
+        if (b.ptr) (void)hipFree(b.ptr);
+    if (ctx->host_scalars) (void)hipHostFree(ctx->host_scalars);
+    delete ctx;
+    return KHC_OK;
+}
+
+const char *khc_last_error(const khc_ctx *ctx) {
+    if (!ctx) return "null context";
+    return ctx->err.c_str();
+}
+
+int khc_set_option(khc_ctx *ctx, int option, int64_t value) {
+    if (!ctx) return KHC_EINVAL;
+    switch (option) {
+        case KHC_OPT_MAX_WIDTH:
+            if (value < 1 || value > kMaxWidth || (value & (value - 1)))
+                return set_error(ctx, KHC_EINVAL, "max width must be a power of two in [1, 32]");
+            ctx->max_width = (int)value;
+            return KHC_OK;
+        case KHC_OPT_SCHEDULE:
+            if (value != 0 && value != 1) return set_error(ctx, KHC_EINVAL, "schedule must be 0 or 1");
+            ctx->schedule = (int)value;
+            return KHC_OK;
+        case KHC_OPT_WORKSPACE_LIMIT:
+            if (value < 0) return set_error(ctx, KHC_EINVAL, "workspace limit must be >= 0");
+            ctx->ws_limit = (uint64_t)value;
+            return KHC_OK;
+        case KHC_OPT_VALIDATE:
+            ctx->validate = value ? 1 : 0;
+            return KHC_OK;
+        case KHC_OPT_WAVES_PER_CU:
+            if (value < 1 || value > 32) return set_error(ctx, KHC_EINVAL, "waves per CU must be in [1, 32]");
+            ctx->waves_per_cu = (int)value;
+            return KHC_OK;
+        default:
+            return set_error(ctx, KHC_EINVAL, "unknown option " + std::to_string(option));
+    }
+}
+
+int khc_validate_csr(khc_ctx *ctx, const khc_csr *g) {
+    if (!ctx) return KHC_EINVAL;
+    if (ctx->sticky) return KHC_EHIP;
+    (void)hipSetDevice(ctx->device);
+    return validate_impl(ctx, g);
+}
+
+int khc_graph_create(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
+    if (!ctx) return KHC_EINVAL;
+    if (!out) return set_error(ctx, KHC_EINVAL, "out is null");
+    *out = nullptr;
+    if (ctx->sticky) return set_error(ctx, KHC_EHIP, "context has a sticky HIP error");
+    (void)hipSetDevice(ctx->device);
+    int rc = check_csr_args(ctx, g);
+    if (rc) return rc;
+    if (ctx->validate && (rc = validate_impl(ctx, g))) return rc;
+
+    // Row schedule: degrees from the offsets, light rows bucketed by degree
+    // (descending), heavy rows sorted by degree and cut into chunks.
+    const uint32_t n = g->n;
+    std::vector<uint64_t> rp(n + 1);
+    hipError_t e = hipMemcpyAsync(rp.data(), g->row_ptr, (n + 1) * sizeof(uint64_t),
+                                  hipMemcpyDeviceToHost, ctx->stream);
+    if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
+    if (e != hipSuccess) return check_hip(ctx, e, "row_ptr download");
+    if (rp[n] != g->nnz) return set_error(ctx, KHC_EGRAPH, "row_ptr[n] != nnz");
+    std::vector<uint32_t> bucket(kHeavyRowArcs + 2, 0);
+    std::vector<uint32_t> heavy;
+    uint32_t maxdeg = 0;
+    for (uint32_t v = 0; v < n; ++v) {
+        uint64_t d = rp[v + 1] - rp[v];
+        if (d > maxdeg) maxdeg = (uint32_t)std::min<uint64_t>(d, 0xFFFFFFFFu);
+        if (d > kHeavyRowArcs) heavy.push_back(v);
+        else bucket[kHeavyRowArcs - d]++;  // descending degree order
+    }
+    std::vector<uint32_t> start(kHeavyRowArcs + 2, 0);
+    for (uint32_t i = 1; i < start.size(); ++i) start[i] = start[i - 1] + bucket[i - 1];
+    std::vector<uint32_t> light(n - heavy.size());
+    for (uint32_t v = 0; v < n; ++v) {
+        uint64_t d = rp[v + 1] - rp[v];
+        if (d <= kHeavyRowArcs) light[start[kHeavyRowArcs - d]++] = v;
+    }
+    std::sort(heavy.begin(), heavy.end(), [&](uint32_t a, uint32_t b) {
+        uint64_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
+        return da != db ? da > db : a < b;
+    });
+    std::vector<uint32_t> chunk_heavy, chunk_first(heavy.size() + 1, 0);
+    for (uint32_t i = 0; i < heavy.size(); ++i) {
+        uint64_t d = rp[heavy[i] + 1] - rp[heavy[i]];
+        uint32_t nch = (uint32_t)((d + kChunkArcs - 1) / kChunkArcs);
+        chunk_first[i] = (uint32_t)chunk_heavy.size();
+        for (uint32_t c = 0; c < nch; ++c) chunk_heavy.push_back(i);
+    }
+    chunk_first[heavy.size()] = (uint32_t)chunk_heavy.size();
+
+    khc_graph *gr = new khc_graph();
+    gr->ctx = ctx;
+    gr->n = n;
+    gr->nnz = g->nnz;
+    gr->row_ptr = g->row_ptr;
+    gr->col = g->col;
+    gr->n_light = (uint32_t)light.size();
+    gr->n_heavy = (uint32_t)heavy.size();
+    gr->n_chunks = (uint32_t)chunk_heavy.size();
+    gr->max_degree = maxdeg;
+    if ((rc = upload(ctx, light, &gr->light_rows)) || (rc = upload(ctx, heavy, &gr->heavy_rows)) ||
+        (rc = upload(ctx, chunk_heavy, &gr->chunk_heavy)) ||
+        (rc = upload(ctx, chunk_first, &gr->chunk_first))) {
+        khc_graph_destroy(gr);
+        return rc;
+    }
+    *out = gr;
+    return KHC_OK;
+}
+
+int khc_graph_destroy(khc_graph *g) {
+    if (!g) return KHC_EINVAL;
+    if (g->ctx) (void)hipStreamSynchronize(g->ctx->stream);
+    if (g->light_rows) (void)hipFree(g->light_rows);
+    if (g->heavy_rows) (void)hipFree(g->heavy_rows);
+    if (g->chunk_heavy) (void)hipFree(g->chunk_heavy);
+    if (g->chunk_first) (void)hipFree(g->chunk_first);
+    delete g;
+    return KHC_OK;
+}
+
+int khdeg_compute(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                  uint32_t *deg) {
+    if (!ctx) return KHC_EINVAL;
+    if (ctx->sticky) return set_error(ctx, KHC_EHIP, "context has a sticky HIP error");
+    if (!g || !deg) return set_error(ctx, KHC_EINVAL, "graph or output is null");
+    if (h == 0) return set_error(ctx, KHC_EINVAL, "h must be >= 1");
+    (void)hipSetDevice(ctx->device);
+    hipStream_t st = ctx->stream;
+    const uint32_t n = g->n;
+    if (n == 0) return KHC_OK;
+    int rc;
+    void *srcs, *cnt;
+    if ((rc = ws_get(ctx, WS_SRCS, (size_t)n * 4, &srcs)) || (rc = ws_get(ctx, WS_FLAGS, 64, &cnt)))
+        return rc;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, deg, 0u,
+                       (uint64_t)n);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)cnt, 0u, (uint64_t)1);
+    hipLaunchKernelGGL(compact_sources_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr,
+                       g->col, alive, (uint32_t *)srcs, (uint32_t *)cnt);
+    hipError_t e = hipMemcpyAsync(ctx->host_scalars, cnt, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(ctx, e, "source compaction");
+    const uint32_t nsrc = ctx->host_scalars[0];
+    return msbfs_degrees(ctx, g, alive, h, (const uint32_t *)srcs, nsrc, nullptr, 1, deg);
+}
+
+int khdeg_compute_list(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                       const uint32_t *verts, uint32_t count, uint32_t *deg) {
+    if (!ctx) return KHC_EINVAL;
+    if (ctx->sticky) return set_error(ctx, KHC_EHIP, "context has a sticky HIP error");
+    if (!g || (count && (!verts || !deg))) return set_error(ctx, KHC_EINVAL, "null argument");
+    if (h == 0) return set_error(ctx, KHC_EINVAL, "h must be >= 1");
+    if (count == 0) return KHC_OK;
+    (void)hipSetDevice(ctx->device);
+    return msbfs_degrees(ctx, g, alive, h, verts, count, deg, 0, nullptr);
+}
+
+}  // extern "C"

@@ -1,0 +1,114 @@
+// Internal declarations shared by the library's HIP sources.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "khcore.h"
+
+namespace khc {
+
+// Rows with more arcs than this are split into chunks of kChunkArcs arcs
+// that whole workgroups process; lighter rows go to one lane group each.
+constexpr uint32_t kHeavyRowArcs = 512;
+constexpr uint32_t kChunkArcs = 4096;
+constexpr int kBlockThreads = 256;  // 4 wavefronts of 64 lanes
+constexpr int kMaxWidth = 32;       // uint64 words per vertex per BFS batch
+
+// Lane layout of one vertex row of W uint64 words inside a wavefront:
+// each lane owns WPL consecutive words (one 16-byte load when WPL == 2) and
+// LPR lanes cover a row, so a wavefront works on 64 / LPR rows at once.
+template <int W>
+struct RowLayout {
+    static constexpr int WPL = (W >= 2) ? 2 : 1;
+    static constexpr int LPR = W / WPL;
+    static constexpr int RPW = 64 / LPR;
+    static constexpr int GROUPS = kBlockThreads / LPR;  // lane groups per workgroup
+};
+
+// A device buffer that only grows.
+struct DevBuf {
+    void *ptr = nullptr;
+    size_t bytes = 0;
+};
+
+struct Workspace;
+
+}  // namespace khc
+
+struct khc_ctx {
+    int device = 0;
+    hipStream_t stream = nullptr;
+    int num_cu = 256;
+    std::string err;
+    int sticky = 0;
+    // options
+    int max_width = 16;
+    int schedule = 1;
+    uint64_t ws_limit = 0;
+    int validate = 1;
+    int waves_per_cu = 4;
+    // workspace
+    std::vector<khc::DevBuf> bufs;
+    uint64_t ws_bytes = 0;
+    // pinned host scalars for per-round readbacks
+    uint32_t *host_scalars = nullptr;
+};
+
+struct khc_graph {
+    khc_ctx *ctx = nullptr;
+    uint32_t n = 0;
+    uint64_t nnz = 0;
+    const uint64_t *row_ptr = nullptr;
+    const uint32_t *col = nullptr;
+    // row schedule (device)
+    uint32_t *light_rows = nullptr;  // rows with <= kHeavyRowArcs arcs, by degree descending
+    uint32_t n_light = 0;
+    uint32_t *heavy_rows = nullptr;  // heavier rows, by degree descending
+    uint32_t n_heavy = 0;
+    uint32_t *chunk_heavy = nullptr;  // heavy-row index of each chunk
+    uint32_t *chunk_first = nullptr;  // first chunk of each heavy row [n_heavy + 1]
+    uint32_t n_chunks = 0;
+    uint32_t max_degree = 0;
+};
+
+namespace khc {
+
+int set_error(khc_ctx *ctx, int code, const std::string &msg);
+int check_hip(khc_ctx *ctx, hipError_t e, const char *what);
+// Workspace slot `slot` of at least `bytes` bytes (grown on demand).
+int ws_get(khc_ctx *ctx, int slot, size_t bytes, void **out);
+
+enum WsSlot {
+    WS_VIS = 0,
+    WS_FRT0,
+    WS_FRT1,
+    WS_FNZ,
+    WS_HACC,
+    WS_HDONE,
+    WS_COUNTS,
+    WS_SRCS,
+    WS_MISC,
+    WS_ALIVE,
+    WS_DEG,
+    WS_DHM1,
+    WS_LB,
+    WS_FLAGS,
+    WS_QUEUE0,
+    WS_QUEUE1,
+    WS_MARK,
+    WS_SCRATCH,
+    WS_NUM_SLOTS
+};
+
+// Multi-source h-bounded BFS over up to 64*max_width sources per batch;
+// writes deg_out[i] = d^h(srcs[i]) for i < nsrc (device list).  `alive` is
+// a device uint8 mask or null.  Asynchronous.
+int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                  const uint32_t *srcs, uint32_t nsrc, uint32_t *deg_out, int scatter,
+                  uint32_t *deg_full);
+
+}  // namespace khc

@@ -1,0 +1,210 @@
+"""Python binding of libkhcore.so (ctypes): argument marshalling only.
+
+Every computation runs in the library's HIP kernels; torch is used here for
+device memory and streams.  The binding refuses to work without the built
+library: there is no host fallback.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkhcore.so")
+
+KHC_OK = 0
+KHC_EINVAL = -1
+KHC_EGRAPH = -2
+KHC_ENOMEM = -3
+KHC_EHIP = -4
+KHC_ELIMIT = -5
+
+OPT_MAX_WIDTH = 1
+OPT_SCHEDULE = 2
+OPT_WORKSPACE_LIMIT = 3
+OPT_VALIDATE = 4
+OPT_WAVES_PER_CU = 5
+
+EXPORTED = [
+    "khc_create", "khc_destroy", "khc_last_error", "khc_set_option",
+    "khc_graph_create", "khc_graph_destroy", "khc_validate_csr",
+    "khdeg_compute", "khdeg_compute_list", "khcore_decompose",
+]
+
+
+class KhcError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__(f"khcore error {code}: {msg}")
+        self.code = code
+
+
+class CSRStruct(ctypes.Structure):
+    _fields_ = [("n", ctypes.c_uint32), ("nnz", ctypes.c_uint64),
+                ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class Stats(ctypes.Structure):
+    _fields_ = [("rounds", ctypes.c_uint64), ("h_recomputes", ctypes.c_uint64),
+                ("hm1_recomputes", ctypes.c_uint64), ("bfs_batches", ctypes.c_uint64),
+                ("affected_total", ctypes.c_uint64), ("max_level", ctypes.c_uint32),
+                ("width_words", ctypes.c_uint32), ("wall_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {name: getattr(self, name) for name, _ in self._fields_}
+
+
+_lib = None
+
+
+def load_library(path: str = LIB_PATH):
+    """Load libkhcore.so and declare its signatures.  Raises if missing."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run __graft_entry__.build() "
+                          "or python -m paper_2006_03372_amd.build")
+    lib = ctypes.CDLL(path)
+    P, u32, u64, i32, i64 = ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_int, ctypes.c_int64
+    PP = ctypes.POINTER(ctypes.c_void_p)
+    sig = {
+        "khc_create": ([PP, i32, P], i32),
+        "khc_destroy": ([P], i32),
+        "khc_last_error": ([P], ctypes.c_char_p),
+        "khc_set_option": ([P, i32, i64], i32),
+        "khc_graph_create": ([P, ctypes.POINTER(CSRStruct), PP], i32),
+        "khc_graph_destroy": ([P], i32),
+        "khc_validate_csr": ([P, ctypes.POINTER(CSRStruct)], i32),
+        "khdeg_compute": ([P, P, P, u32, P], i32),
+        "khdeg_compute_list": ([P, P, P, u32, P, u32, P], i32),
+        "khcore_decompose": ([P, P, u32, P, P, ctypes.POINTER(Stats)], i32),
+    }
+    for name, (args, res) in sig.items():
+        f = getattr(lib, name)
+        f.argtypes = args
+        f.restype = res
+    _lib = lib
+    return lib
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def _dptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+class Context:
+    """A library context bound to one device and one HIP stream."""
+
+    def __init__(self, device: int = 0, stream=None):
+        torch = _torch()
+        self.lib = load_library()
+        if not torch.cuda.is_available():
+            raise RuntimeError("no GPU visible: the khcore library needs an MI355X")
+        self.device = device
+        self.stream = stream if stream is not None else torch.cuda.current_stream(device)
+        h = ctypes.c_void_p()
+        rc = self.lib.khc_create(ctypes.byref(h), device, ctypes.c_void_p(self.stream.cuda_stream))
+        if rc:
+            raise KhcError(rc, "khc_create failed")
+        self.handle = h
+
+    def _check(self, rc):
+        if rc:
+            msg = self.lib.khc_last_error(self.handle)
+            raise KhcError(rc, msg.decode() if msg else "")
+
+    def set_option(self, option: int, value: int):
+        self._check(self.lib.khc_set_option(self.handle, option, int(value)))
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.lib.khc_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()
+
+    # -------------------------------------------------------------- graph
+    def graph(self, g) -> "Graph":
+        """Upload a host CSR (synth.CSR) and build its row schedule."""
+        return Graph(self, g)
+
+    def validate(self, row_ptr, col, n: int) -> int:
+        """Validate a device CSR; returns the status code (0 = ok)."""
+        s = CSRStruct(n, int(row_ptr[-1].item()) if row_ptr.numel() else 0,
+                      _dptr(row_ptr), _dptr(col))
+        return self.lib.khc_validate_csr(self.handle, ctypes.byref(s))
+
+    # ------------------------------------------------------------ compute
+    def hdeg(self, graph: "Graph", h: int, alive=None, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+        self._check(self.lib.khdeg_compute(self.handle, graph.handle, _dptr(alive), h, _dptr(out)))
+        return out
+
+    def hdeg_list(self, graph: "Graph", h: int, verts, alive=None, out=None):
+        torch = _torch()
+        if out is None:
+            out = torch.empty(verts.numel(), dtype=torch.int32, device=graph.device)
+        self._check(self.lib.khdeg_compute_list(self.handle, graph.handle, _dptr(alive), h,
+                                                _dptr(verts), verts.numel(), _dptr(out)))
+        return out
+
+    def core(self, graph: "Graph", h: int, with_round: bool = False, core=None, rnd=None):
+        torch = _torch()
+        if core is None:
+            core = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+        if with_round and rnd is None:
+            rnd = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+        st = Stats()
+        self._check(self.lib.khcore_decompose(self.handle, graph.handle, h, _dptr(core),
+                                              _dptr(rnd) if with_round else None,
+                                              ctypes.byref(st)))
+        return core, (rnd if with_round else None), st.as_dict()
+
+
+class Graph:
+    """A device CSR plus the library's graph handle."""
+
+    def __init__(self, ctx: Context, g, validate: bool = True):
+        torch = _torch()
+        self.ctx = ctx
+        self.n = int(g.n)
+        self.nnz = int(g.row_ptr[-1]) if len(g.row_ptr) else 0
+        self.device = torch.device("cuda", ctx.device)
+        self.row_ptr = torch.from_numpy(np.ascontiguousarray(g.row_ptr).view(np.int64)).to(self.device)
+        col = np.ascontiguousarray(g.col, dtype=np.uint32)
+        if col.size == 0:
+            col = np.zeros(1, dtype=np.uint32)
+        self.col = torch.from_numpy(col.view(np.int32)).to(self.device)
+        s = CSRStruct(self.n, self.nnz, _dptr(self.row_ptr), _dptr(self.col))
+        h = ctypes.c_void_p()
+        ctx._check(ctx.lib.khc_graph_create(ctx.handle, ctypes.byref(s), ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            self.ctx.lib.khc_graph_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

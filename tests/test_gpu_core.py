@@ -1,0 +1,102 @@
+"""GPU parity of khcore_decompose with the CPU oracle (bit-exact core numbers
+and removal rounds)."""
+import os
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_03372_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+GOLDEN = os.path.join(os.path.dirname(__file__), "golden")
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2006_03372_amd import khcore
+    c = khcore.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _gpu_core(ctx, g, h, schedule=1, width=16):
+    from paper_2006_03372_amd import khcore
+    ctx.set_option(khcore.OPT_SCHEDULE, schedule)
+    ctx.set_option(khcore.OPT_MAX_WIDTH, width)
+    gr = ctx.graph(g)
+    c, r, st = ctx.core(gr, h, with_round=True)
+    out = _u32(c), _u32(r), st
+    gr.close()
+    return out
+
+
+def _check(ctx, g, h, schedules=(0, 1), widths=(16,)):
+    c_ref, r_ref = oracle.peel(g, h)
+    for s in schedules:
+        for w in widths:
+            print(f"core n={g.n} nnz={g.nnz} h={h} schedule={s} width={w}", flush=True)
+            c, r, st = _gpu_core(ctx, g, h, s, w)
+            assert (c == c_ref).all(), (s, w, np.flatnonzero(c != c_ref)[:10])
+            assert (r == r_ref).all(), (s, w, np.flatnonzero(r != r_ref)[:10])
+
+
+@pytest.mark.parametrize("h", [1, 2, 3, 5])
+def test_closed_forms(ctx, h):
+    for n in (2 * h + 1, 2 * h + 4, 17):
+        c, _, _ = _gpu_core(ctx, synth.cycle(n), h)
+        assert (c == 2 * h).all()
+    c, _, _ = _gpu_core(ctx, synth.complete(8), h)
+    assert (c == 7).all()
+    c, _, _ = _gpu_core(ctx, synth.path(12), h)
+    assert (c == min(h, 11)).all()
+    c, _, _ = _gpu_core(ctx, synth.from_edges(5, [0], [1]), h)
+    assert list(c) == [1, 1, 0, 0, 0]
+
+
+def test_running_example(ctx):
+    lines = [ln.split() for ln in open(os.path.join(GOLDEN, "running_example.txt"))
+             if ln.strip() and not ln.startswith("#")]
+    e = np.array([tuple(int(x) - 1 for x in t.split("-")) for t in lines[0][1:]])
+    g = synth.from_edges(14, e[:, 0], e[:, 1])
+    for f in lines[1:]:
+        if f[0] == "core":
+            h = int(f[1].split("=")[1])
+            c, _, _ = _gpu_core(ctx, g, h)
+            assert list(c) == [int(x) for x in f[2:]]
+
+
+@pytest.mark.parametrize("h", [1, 2, 3, 4])
+def test_chung_lu_2000(ctx, h):
+    g = synth.chung_lu(2000, 10.0, 2.5, seed=1)
+    _check(ctx, g, h, widths=(1, 16))
+
+
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_rmat_12(ctx, h):
+    g = synth.rmat(12, 8, seed=1)
+    _check(ctx, g, h)
+
+
+def test_disjoint_union_and_isolated(ctx):
+    parts = [synth.chung_lu(n, m, 2.5, s) for n, m, s in ((300, 5.0, 1), (700, 9.0, 2), (50, 3.0, 3))]
+    g = synth.disjoint_union(parts + [synth.from_edges(9, [], [])])
+    _check(ctx, g, 3)
+
+
+def test_certificate_rmat14_h3(ctx):
+    """R-MAT scale 14, h=3: the peeling-order certificate on sampled
+    vertices plus exact oracle h-degrees of sampled vertices."""
+    g = synth.rmat(14, 8, seed=1)
+    c, r, st = _gpu_core(ctx, g, 3)
+    rng = np.random.default_rng(0)
+    verts = rng.choice(g.n, size=300, replace=False)
+    fail = oracle.certificate(g, 3, c, r, verts)
+    assert fail.sum() == 0, fail
