@@ -1,0 +1,136 @@
+"""Benchmark: h-hop degrees of every vertex of R-MAT scale 20 at h = 3.
+
+One step = khdeg_compute over all vertices of the graph (every live vertex
+gets its exact h-hop degree by the multi-source bounded BFS kernels).  The
+throughput is in GTEPS: traversed edges, where the work of one vertex is the
+number of arcs a scalar bounded BFS from it examines (khdeg_scanned_arcs),
+divided by the step time, 10^9 per second.
+
+Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
+"""
+import argparse
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "h-hop BFS GTEPS + (k,h)-core wall time, R-MAT-20 h=3; learned-mode error"
+HBM_PEAK_GBS = 8000.0
+
+
+def log(msg):
+    print(msg, file=sys.stderr, flush=True)
+
+
+def cpu_baseline(g, h, budget_s=15.0, seed=0):
+    """The oracle's scalar bounded BFS on a bounded random sample of the
+    sources, single thread: traversed edges per second."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    deg = g.degrees()
+    cand = np.flatnonzero(deg > 0).astype(np.uint32)
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(cand)
+    done_te, done_v, t_used = 0, 0, 0.0
+    chunk = 16
+    while t_used < budget_s and done_v < order.size:
+        verts = order[done_v:done_v + chunk]
+        t = time.perf_counter()
+        _, te = oracle.hdeg_list(g, h, verts)
+        t_used += time.perf_counter() - t
+        done_te += int(te.sum())
+        done_v += verts.size
+    return {"value": done_te / t_used / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+            "sample": f"{done_v} random non-isolated sources of the same graph, h={h}, "
+                      f"scalar bounded BFS (oracle_hdeg_list), {t_used:.1f} s"}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--scale", type=int, default=20)
+    ap.add_argument("--edge-factor", type=int, default=16)
+    ap.add_argument("--h", type=int, default=3)
+    ap.add_argument("--width", type=int, default=32)
+    ap.add_argument("--no-cpu", action="store_true")
+    args = ap.parse_args()
+    if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
+        print("bench.py runs on one GPU only: this build measures the single-GPU path "
+              "(--gpus 1); multi-GPU sharding is not implemented.", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+    from paper_2006_03372_amd import khcore, synth
+
+    t = time.time()
+    g = synth.rmat(args.scale, args.edge_factor, seed=1)
+    log(f"generated R-MAT scale {args.scale} ef {args.edge_factor}: n={g.n} edges={g.num_edges} "
+        f"({time.time() - t:.1f} s)")
+    ctx = khcore.Context(0)
+    ctx.set_option(khcore.OPT_MAX_WIDTH, args.width)
+    gr = ctx.graph(g)
+    h = args.h
+
+    te = ctx.scanned_arcs(gr, h)
+    torch.cuda.synchronize()
+    te_total = int(te.cpu().numpy().view(np.uint64).sum())
+    del te
+    log(f"traversed-edge total at h={h}: {te_total:.4e}")
+
+    for i in range(args.warmup):
+        ctx.hdeg(gr, h)
+        torch.cuda.synchronize()
+        log(f"warmup {i + 1}/{args.warmup} done")
+
+    ctx.set_option(khcore.OPT_PROFILE, 1)
+    ctx.profile_read(reset=True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        out = ctx.hdeg(gr, h)
+        torch.cuda.synchronize()
+        log(f"step {i + 1}/{args.steps} done")
+    t1 = time.perf_counter()
+    prof = ctx.profile_read(reset=True)
+    ctx.set_option(khcore.OPT_PROFILE, 0)
+    ms_per_step = (t1 - t0) * 1e3 / args.steps
+    gteps = te_total / (ms_per_step / 1e3) / 1e9
+
+    last = prof["level_last"]
+    avg_ms = last["ms"] / max(last["launches"], 1)
+    avg_bytes = last["bytes"] / max(last["launches"], 1)
+    achieved = avg_bytes / (avg_ms / 1e3) / 1e9
+    roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "kernel": f"level_kernel<W,LAST> (counting level), {last['launches']} launches, "
+                          f"avg {avg_ms:.3f} ms, {avg_bytes / 1e9:.3f} GB algorithmic per launch"}
+
+    result = {
+        "metric": METRIC, "value": round(gteps, 2), "unit": "GTEPS", "n_gpus": 1,
+        "steps": args.steps, "warmup": args.warmup, "ms_per_step": round(ms_per_step, 2),
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "u64",
+        "data": "synthetic",
+        "config": {"workload": f"khdeg_compute, all vertices, R-MAT scale {args.scale} "
+                               f"(ef {args.edge_factor}, a/b/c/d .57/.19/.19/.05, seed 1), h={h}",
+                   "n": g.n, "edges": g.num_edges, "h": h, "max_width_words": args.width,
+                   "traversed_edges": te_total},
+        "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 2)} for k, v in prof.items()},
+        "roofline": roofline,
+    }
+    if not args.no_cpu:
+        log("timing the CPU oracle on a sample ...")
+        result["cpu_baseline"] = cpu_baseline(g, h)
+    gr.close()
+    ctx.close()
+    print(json.dumps(result), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -82,8 +82,25 @@ const char *khc_last_error(const khc_ctx *ctx);
 #define KHC_OPT_SCHEDULE 2        /* 0 = plain recompute of the affected set, 1 = bounded (default)     */
 #define KHC_OPT_WORKSPACE_LIMIT 3 /* cap on workspace bytes (0 = none)                                  */
 #define KHC_OPT_VALIDATE 4        /* 1 = validate the CSR in khc_graph_create (default 1)               */
-#define KHC_OPT_WAVES_PER_CU 5    /* persistent workgroups per CU for BFS levels (1..16; default 4)     */
+#define KHC_OPT_WAVES_PER_CU 5    /* wavefronts per CU for the BFS level kernels (4..32; default 16)     */
+#define KHC_OPT_PROFILE 6         /* 1 = time every BFS kernel launch with HIP events (default 0)       */
 int khc_set_option(khc_ctx *ctx, int option, int64_t value);
+
+/* Kernel timing collected while KHC_OPT_PROFILE is 1, per kernel class:
+ * 0 batch clear, 1 first BFS level, 2 inner BFS levels, 3 last BFS level
+ * (the counting level).  bytes[c] sums the algorithmic bytes of the pull
+ * levels of that class whose live set is the whole graph:
+ * n*(8 + 8W) + nnz*(4 + 8W) per launch (row offset + own words per row,
+ * column id + gathered frontier words per arc); 0 where not known. */
+typedef struct {
+    uint64_t launches[4];
+    double ms[4];
+    double bytes[4];
+} khc_profile;
+
+/* Waits for the recorded launches, adds them into *out and, if reset != 0,
+ * forgets them.  Timing is taken on the context stream with HIP events. */
+int khc_profile_read(khc_ctx *ctx, khc_profile *out, int reset);
 
 /* ---- graph store ------------------------------------------------------ */
 
@@ -112,6 +129,15 @@ int khdeg_compute(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
  *   verts  device uint32[count]; alive as above.  Asynchronous. */
 int khdeg_compute_list(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                        const uint32_t *verts, uint32_t count, uint32_t *deg);
+
+/* Work measure for traversed-edges-per-second figures: te[v] = the number
+ * of arcs a scalar bounded BFS from v examines, i.e. the live degree summed
+ * over every live vertex within h-1 hops of v (v included).  Dead vertices
+ * get 0.  The paper reports run times only; this count is the work unit
+ * its BFS-based h-degree computation performs per vertex.
+ *   te     device uint64[n] output.  Asynchronous. */
+int khdeg_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                       uint64_t *te);
 
 /* ---- (k,h)-core decomposition ----------------------------------------- */
 

@@ -17,6 +17,32 @@ int set_error(khc_ctx *ctx, int code, const std::string &msg) {
     return code;
 }
 
+int prof_begin(khc_ctx *ctx, int cls, double bytes) {
+    if (!ctx->profile) return -1;
+    khc_ctx::ProfRec r;
+    for (int i = 0; i < 2; ++i) {
+        hipEvent_t ev;
+        if (!ctx->prof_pool.empty()) {
+            ev = ctx->prof_pool.back();
+            ctx->prof_pool.pop_back();
+        } else if (hipEventCreate(&ev) != hipSuccess) {
+            (void)hipGetLastError();
+            return -1;
+        }
+        (i == 0 ? r.a : r.b) = ev;
+    }
+    r.cls = cls;
+    r.bytes = bytes;
+    (void)hipEventRecord(r.a, ctx->stream);
+    ctx->prof_pending.push_back(r);
+    return (int)ctx->prof_pending.size() - 1;
+}
+
+void prof_end(khc_ctx *ctx, int rec) {
+    if (rec < 0) return;
+    (void)hipEventRecord(ctx->prof_pending[rec].b, ctx->stream);
+}
+
 int check_hip(khc_ctx *ctx, hipError_t e, const char *what) {
     if (e == hipSuccess) return KHC_OK;
     if (ctx) ctx->sticky = 1;
@@ -246,6 +272,11 @@ int khc_destroy(khc_ctx *ctx) {
     (void)hipStreamSynchronize(ctx->stream);
     for (auto &b : ctx->bufs)
         if (b.ptr) (void)hipFree(b.ptr);
+    for (auto &r : ctx->prof_pending) {
+        (void)hipEventDestroy(r.a);
+        (void)hipEventDestroy(r.b);
+    }
+    for (auto ev : ctx->prof_pool) (void)hipEventDestroy(ev);
     if (ctx->host_scalars) (void)hipHostFree(ctx->host_scalars);
     delete ctx;
     return KHC_OK;
@@ -276,12 +307,41 @@ int khc_set_option(khc_ctx *ctx, int option, int64_t value) {
             ctx->validate = value ? 1 : 0;
             return KHC_OK;
         case KHC_OPT_WAVES_PER_CU:
-            if (value < 1 || value > 32) return set_error(ctx, KHC_EINVAL, "waves per CU must be in [1, 32]");
+            if (value < 4 || value > 32) return set_error(ctx, KHC_EINVAL, "waves per CU must be in [4, 32]");
             ctx->waves_per_cu = (int)value;
+            return KHC_OK;
+        case KHC_OPT_PROFILE:
+            ctx->profile = value ? 1 : 0;
             return KHC_OK;
         default:
             return set_error(ctx, KHC_EINVAL, "unknown option " + std::to_string(option));
     }
+}
+
+int khc_profile_read(khc_ctx *ctx, khc_profile *out, int reset) {
+    if (!ctx) return KHC_EINVAL;
+    (void)hipSetDevice(ctx->device);
+    for (auto &r : ctx->prof_pending) {
+        float ms = 0.f;
+        hipError_t e = hipEventSynchronize(r.b);
+        if (e == hipSuccess) e = hipEventElapsedTime(&ms, r.a, r.b);
+        if (e != hipSuccess) return check_hip(ctx, e, "profile event");
+        ctx->prof_acc.launches[r.cls] += 1;
+        ctx->prof_acc.ms[r.cls] += ms;
+        ctx->prof_acc.bytes[r.cls] += r.bytes;
+        ctx->prof_pool.push_back(r.a);
+        ctx->prof_pool.push_back(r.b);
+    }
+    ctx->prof_pending.clear();
+    if (out) {
+        for (int c = 0; c < 4; ++c) {
+            out->launches[c] += ctx->prof_acc.launches[c];
+            out->ms[c] += ctx->prof_acc.ms[c];
+            out->bytes[c] += ctx->prof_acc.bytes[c];
+        }
+    }
+    if (reset) ctx->prof_acc = khc_profile{};
+    return KHC_OK;
 }
 
 int khc_validate_csr(khc_ctx *ctx, const khc_csr *g) {
@@ -394,6 +454,31 @@ int khdeg_compute(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
     if (e != hipSuccess) return check_hip(ctx, e, "source compaction");
     const uint32_t nsrc = ctx->host_scalars[0];
     return msbfs_degrees(ctx, g, alive, h, (const uint32_t *)srcs, nsrc, nullptr, 1, deg);
+}
+
+int khdeg_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                       uint64_t *te) {
+    if (!ctx) return KHC_EINVAL;
+    if (ctx->sticky) return set_error(ctx, KHC_EHIP, "context has a sticky HIP error");
+    if (!g || !te) return set_error(ctx, KHC_EINVAL, "graph or output is null");
+    if (h == 0) return set_error(ctx, KHC_EINVAL, "h must be >= 1");
+    (void)hipSetDevice(ctx->device);
+    hipStream_t st = ctx->stream;
+    const uint32_t n = g->n;
+    if (n == 0) return KHC_OK;
+    int rc;
+    void *srcs, *cnt;
+    if ((rc = ws_get(ctx, WS_SRCS, (size_t)n * 4, &srcs)) || (rc = ws_get(ctx, WS_FLAGS, 64, &cnt)))
+        return rc;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for((uint64_t)n * 2, 256, 4096)), dim3(256), 0, st,
+                       (uint32_t *)te, 0u, (uint64_t)n * 2);
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)cnt, 0u, (uint64_t)1);
+    hipLaunchKernelGGL(compact_sources_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr,
+                       g->col, alive, (uint32_t *)srcs, (uint32_t *)cnt);
+    hipError_t e = hipMemcpyAsync(ctx->host_scalars, cnt, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(ctx, e, "source compaction");
+    return msbfs_scanned_arcs(ctx, g, alive, h, (const uint32_t *)srcs, ctx->host_scalars[0], te);
 }
 
 int khdeg_compute_list(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,

@@ -369,6 +369,61 @@ __global__ void batch_scatter_kernel(const uint32_t *srcs, uint32_t first, uint3
     }
 }
 
+// Scanned-arc totals: for every source lane, the sum over vertices it has
+// reached (within h-1 hops, including itself) of their live degree, i.e. the
+// arcs a scalar bounded BFS from that source examines.  One thread per
+// (row, word); LDS totals per lane, flushed with 64-bit atomics.
+template <int W>
+__global__ __launch_bounds__(256) void scanned_arcs_kernel(uint32_t n, const uint64_t *row_ptr,
+                                                           const uint32_t *col, const uint8_t *alive,
+                                                           const uint64_t *vis,
+                                                           unsigned long long *te) {
+    __shared__ unsigned long long s_te[64 * W];
+    for (int i = threadIdx.x; i < 64 * W; i += blockDim.x) s_te[i] = 0;
+    __syncthreads();
+    const size_t total = (size_t)n * W;
+    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < total;
+         i += (size_t)gridDim.x * blockDim.x) {
+        uint64_t word = vis[i];
+        if (!word) continue;
+        const uint32_t y = (uint32_t)(i / W);
+        const int j = (int)(i % W);
+        uint64_t dy = 0;
+        if (!alive) {
+            dy = row_ptr[y + 1] - row_ptr[y];
+        } else {
+            for (uint64_t a = row_ptr[y]; a < row_ptr[y + 1]; ++a) dy += alive[col[a]] ? 1u : 0u;
+        }
+        while (word) {
+            const int b = __builtin_ctzll(word);
+            word &= word - 1;
+            atomicAdd(&s_te[j * 64 + b], (unsigned long long)dy);
+        }
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i < 64 * W; i += blockDim.x)
+        if (s_te[i]) atomicAdd(&te[i], s_te[i]);
+}
+
+__global__ void te_scatter_kernel(const uint32_t *srcs, uint32_t first, uint32_t cnt,
+                                  const unsigned long long *te, uint64_t *te_full) {
+    const uint32_t l = blockIdx.x * blockDim.x + threadIdx.x;
+    if (l >= cnt) return;
+    const uint32_t s = srcs ? srcs[first + l] : first + l;
+    te_full[s] = te[l];
+}
+
+__global__ void zero_u64_kernel(unsigned long long *p, int count) {
+    for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0;
+}
+
+template <int W>
+void launch_scanned(int grid, hipStream_t st, uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                    const uint8_t *alive, const uint64_t *vis, unsigned long long *te) {
+    hipLaunchKernelGGL((scanned_arcs_kernel<W>), dim3(grid), dim3(256), 0, st, n, row_ptr, col, alive,
+                       vis, te);
+}
+
 template <int W>
 void launch_level(const LevelParams &p, int grid, bool last, hipStream_t st) {
     if (last)
@@ -396,10 +451,12 @@ int width_for(uint32_t cnt, int max_width) {
 
 }  // namespace
 
-int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
-                  const uint32_t *srcs, uint32_t nsrc, uint32_t *deg_list, int scatter,
-                  uint32_t *deg_full) {
+int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+              const uint32_t *srcs, uint32_t nsrc, uint32_t *deg_list, int scatter,
+              uint32_t *deg_full, uint64_t *te_full) {
     if (nsrc == 0) return KHC_OK;
+    // scanned-arc mode: expand h-1 levels, then weight the reached vertices
+    const uint32_t levels = te_full ? h - 1 : h;
     const uint32_t n = g->n;
     const int maxW = ctx->max_width;
     const size_t words = (size_t)n * maxW;
@@ -415,6 +472,8 @@ int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
         (rc = ws_get(ctx, WS_COUNTS, (size_t)64 * kMaxWidth * 4, &counts)) ||
         (rc = ws_get(ctx, WS_MISC, ((size_t)2 * h + 4) * 4, &misc)))
         return rc;
+    void *te = nullptr;
+    if (te_full && (rc = ws_get(ctx, WS_LB, (size_t)64 * kMaxWidth * 8, &te))) return rc;
     uint32_t *fnzp = (uint32_t *)fnz;
     // misc: [0, h] level work counters, [h+1, 2h+2] frontier row counts
     uint32_t *miscp = (uint32_t *)misc;
@@ -430,12 +489,14 @@ int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
         int cgrid = (int)((bw + 255) / 256);
         if (cgrid > ctx->num_cu * 8) cgrid = ctx->num_cu * 8;
         if (cgrid < 1) cgrid = 1;
+        int prec = prof_begin(ctx, 0, 0.0);
         hipLaunchKernelGGL(batch_clear_kernel, dim3(cgrid), dim3(256), 0, st, (uint64_t *)vis,
                            (uint64_t *)f0, (uint64_t *)f1, bw, fnzp, (size_t)fnz_words * 3,
                            (uint32_t *)counts, 64 * W, miscp, (int)(2 * h + 3));
+        prof_end(ctx, prec);
         hipLaunchKernelGGL(batch_seed_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, srcs,
                            first, cnt, W, alive, (uint64_t *)vis, (uint64_t *)f0, fnzp, fcp);
-        for (uint32_t lev = 1; lev <= h; ++lev) {
+        for (uint32_t lev = 1; lev <= levels; ++lev) {
             LevelParams p;
             p.row_ptr = g->row_ptr;
             p.col = g->col;
@@ -459,14 +520,48 @@ int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
             p.n = n;
             p.n_light = g->n_light;
             p.n_chunks = g->n_chunks;
-            p.fnz_words = (lev + 1 <= h) ? fnz_words : 0u;
-            dispatch_level(W, p, grid, lev == h, st);
+            p.fnz_words = (lev + 1 <= levels) ? fnz_words : 0u;
+            // algorithmic bytes of a pull level over the whole graph
+            const double bytes = alive ? 0.0
+                                       : (double)n * (8.0 + 8.0 * W) + (double)g->nnz * (4.0 + 8.0 * W);
+            const bool last = !te_full && lev == h;
+            prec = prof_begin(ctx, last ? 3 : (lev == 1 ? 1 : 2), bytes);
+            dispatch_level(W, p, grid, last, st);
+            prof_end(ctx, prec);
         }
-        hipLaunchKernelGGL(batch_scatter_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, srcs,
-                           first, cnt, (const uint32_t *)counts, deg_list, scatter ? deg_full : nullptr);
+        if (te_full) {
+            unsigned long long *tep = (unsigned long long *)te;
+            hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, st, tep, 64 * W);
+            const int sgrid = ctx->num_cu * 4;
+            const uint64_t *visp = (const uint64_t *)vis;
+            switch (W) {
+                case 1: launch_scanned<1>(sgrid, st, n, g->row_ptr, g->col, alive, visp, tep); break;
+                case 2: launch_scanned<2>(sgrid, st, n, g->row_ptr, g->col, alive, visp, tep); break;
+                case 4: launch_scanned<4>(sgrid, st, n, g->row_ptr, g->col, alive, visp, tep); break;
+                case 8: launch_scanned<8>(sgrid, st, n, g->row_ptr, g->col, alive, visp, tep); break;
+                case 16: launch_scanned<16>(sgrid, st, n, g->row_ptr, g->col, alive, visp, tep); break;
+                default: launch_scanned<32>(sgrid, st, n, g->row_ptr, g->col, alive, visp, tep); break;
+            }
+            hipLaunchKernelGGL(te_scatter_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, srcs, first,
+                               cnt, (const unsigned long long *)tep, te_full);
+        } else {
+            hipLaunchKernelGGL(batch_scatter_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, srcs,
+                               first, cnt, (const uint32_t *)counts, deg_list, scatter ? deg_full : nullptr);
+        }
         first += cnt;
     }
     return check_hip(ctx, hipGetLastError(), "msbfs launch");
+}
+
+int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                  const uint32_t *srcs, uint32_t nsrc, uint32_t *deg_list, int scatter,
+                  uint32_t *deg_full) {
+    return msbfs_run(ctx, g, alive, h, srcs, nsrc, deg_list, scatter, deg_full, nullptr);
+}
+
+int msbfs_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                       const uint32_t *srcs, uint32_t nsrc, uint64_t *te_full) {
+    return msbfs_run(ctx, g, alive, h, srcs, nsrc, nullptr, 1, nullptr, te_full);
 }
 
 }  // namespace khc

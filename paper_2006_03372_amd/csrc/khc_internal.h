@@ -50,12 +50,22 @@ struct khc_ctx {
     int schedule = 1;
     uint64_t ws_limit = 0;
     int validate = 1;
-    int waves_per_cu = 4;
+    int waves_per_cu = 16;
     // workspace
     std::vector<khc::DevBuf> bufs;
     uint64_t ws_bytes = 0;
     // pinned host scalars for per-round readbacks
     uint32_t *host_scalars = nullptr;
+    // kernel timing (KHC_OPT_PROFILE)
+    int profile = 0;
+    struct ProfRec {
+        hipEvent_t a, b;
+        int cls;
+        double bytes;
+    };
+    std::vector<ProfRec> prof_pending;
+    std::vector<hipEvent_t> prof_pool;
+    khc_profile prof_acc{};
 };
 
 struct khc_graph {
@@ -78,6 +88,10 @@ struct khc_graph {
 namespace khc {
 
 int set_error(khc_ctx *ctx, int code, const std::string &msg);
+// Kernel timing helpers: prof_begin returns a record index (or -1 when
+// profiling is off); prof_end closes it.
+int prof_begin(khc_ctx *ctx, int cls, double bytes);
+void prof_end(khc_ctx *ctx, int rec);
 int check_hip(khc_ctx *ctx, hipError_t e, const char *what);
 // Workspace slot `slot` of at least `bytes` bytes (grown on demand).
 int ws_get(khc_ctx *ctx, int slot, size_t bytes, void **out);
@@ -110,5 +124,10 @@ enum WsSlot {
 int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                   const uint32_t *srcs, uint32_t nsrc, uint32_t *deg_out, int scatter,
                   uint32_t *deg_full);
+
+// te_full[s] = arcs a scalar bounded BFS from s examines (live degree summed
+// over the vertices within h-1 hops of s, s included).  Asynchronous.
+int msbfs_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                       const uint32_t *srcs, uint32_t nsrc, uint64_t *te_full);
 
 }  // namespace khc

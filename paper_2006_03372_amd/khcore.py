@@ -26,11 +26,12 @@ OPT_SCHEDULE = 2
 OPT_WORKSPACE_LIMIT = 3
 OPT_VALIDATE = 4
 OPT_WAVES_PER_CU = 5
+OPT_PROFILE = 6
 
 EXPORTED = [
-    "khc_create", "khc_destroy", "khc_last_error", "khc_set_option",
+    "khc_create", "khc_destroy", "khc_last_error", "khc_set_option", "khc_profile_read",
     "khc_graph_create", "khc_graph_destroy", "khc_validate_csr",
-    "khdeg_compute", "khdeg_compute_list", "khcore_decompose",
+    "khdeg_compute", "khdeg_compute_list", "khdeg_scanned_arcs", "khcore_decompose",
 ]
 
 
@@ -43,6 +44,17 @@ class KhcError(RuntimeError):
 class CSRStruct(ctypes.Structure):
     _fields_ = [("n", ctypes.c_uint32), ("nnz", ctypes.c_uint64),
                 ("row_ptr", ctypes.c_void_p), ("col", ctypes.c_void_p)]
+
+
+class Profile(ctypes.Structure):
+    _fields_ = [("launches", ctypes.c_uint64 * 4), ("ms", ctypes.c_double * 4),
+                ("bytes", ctypes.c_double * 4)]
+
+    CLASSES = ("clear", "level_first", "level_inner", "level_last")
+
+    def as_dict(self):
+        return {c: {"launches": int(self.launches[i]), "ms": float(self.ms[i]),
+                    "bytes": float(self.bytes[i])} for i, c in enumerate(self.CLASSES)}
 
 
 class Stats(ctypes.Structure):
@@ -74,11 +86,13 @@ def load_library(path: str = LIB_PATH):
         "khc_destroy": ([P], i32),
         "khc_last_error": ([P], ctypes.c_char_p),
         "khc_set_option": ([P, i32, i64], i32),
+        "khc_profile_read": ([P, ctypes.POINTER(Profile), i32], i32),
         "khc_graph_create": ([P, ctypes.POINTER(CSRStruct), PP], i32),
         "khc_graph_destroy": ([P], i32),
         "khc_validate_csr": ([P, ctypes.POINTER(CSRStruct)], i32),
         "khdeg_compute": ([P, P, P, u32, P], i32),
         "khdeg_compute_list": ([P, P, P, u32, P, u32, P], i32),
+        "khdeg_scanned_arcs": ([P, P, P, u32, P], i32),
         "khcore_decompose": ([P, P, u32, P, P, ctypes.POINTER(Stats)], i32),
     }
     for name, (args, res) in sig.items():
@@ -122,6 +136,12 @@ class Context:
     def set_option(self, option: int, value: int):
         self._check(self.lib.khc_set_option(self.handle, option, int(value)))
 
+    def profile_read(self, reset: bool = True) -> dict:
+        """Kernel timing recorded while OPT_PROFILE is on (see khc_profile)."""
+        p = Profile()
+        self._check(self.lib.khc_profile_read(self.handle, ctypes.byref(p), int(reset)))
+        return p.as_dict()
+
     def close(self):
         if getattr(self, "handle", None):
             self.lib.khc_destroy(self.handle)
@@ -164,6 +184,14 @@ class Context:
             out = torch.empty(verts.numel(), dtype=torch.int32, device=graph.device)
         self._check(self.lib.khdeg_compute_list(self.handle, graph.handle, _dptr(alive), h,
                                                 _dptr(verts), verts.numel(), _dptr(out)))
+        return out
+
+    def scanned_arcs(self, graph: "Graph", h: int, alive=None, out=None):
+        """Arcs a scalar bounded BFS from each vertex examines (int64)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(graph.n, dtype=torch.int64, device=graph.device)
+        self._check(self.lib.khdeg_scanned_arcs(self.handle, graph.handle, _dptr(alive), h, _dptr(out)))
         return out
 
     def core(self, graph: "Graph", h: int, with_round: bool = False, core=None, rnd=None):

@@ -128,3 +128,18 @@ def test_deterministic(ctx):
     a = _gpu_hdeg(ctx, g, 3)
     b = _gpu_hdeg(ctx, g, 3)
     assert (a == b).all()
+
+
+@pytest.mark.parametrize("h", [1, 2, 3])
+def test_scanned_arcs(ctx, h):
+    g = synth.chung_lu(2000, 10.0, 2.5, seed=1)
+    alive = synth.random_alive(g.n, 0.85, 7)
+    import torch
+    for a in (None, alive):
+        verts = np.arange(g.n, dtype=np.uint32)
+        _, te_ref = oracle.hdeg_list(g, h, verts, a)
+        gr = ctx.graph(g)
+        te = ctx.scanned_arcs(gr, h, None if a is None else torch.from_numpy(a).to(gr.device))
+        got = te.cpu().numpy().view(np.uint64)
+        gr.close()
+        assert (got == te_ref).all()
