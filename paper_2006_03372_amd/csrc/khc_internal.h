@@ -115,6 +115,11 @@ enum WsSlot {
     WS_QUEUE1,
     WS_MARK,
     WS_SCRATCH,
+    WS_FRT2,
+    WS_BQUEUE,
+    WS_QPTRS,
+    WS_TE,
+    WS_HQUEUE,
     WS_NUM_SLOTS
 };
 
