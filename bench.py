@@ -25,6 +25,27 @@ def log(msg):
     print(msg, file=sys.stderr, flush=True)
 
 
+def profiled_traffic(path=os.path.join(ROOT, "profiles", "level_kernel_rmat20_h3.md")):
+    """HBM-side bytes per launch of the counting level from the committed
+    rocprofv3 counter summary, or None when the BFS source has changed
+    since the counters were taken."""
+    import hashlib
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        line = line.strip()
+        for key in ("traffic_bytes_per_launch:", "source_sha256:"):
+            if line.startswith(key):
+                vals[key] = line.split(":", 1)[1].strip()
+    src = os.path.join(ROOT, "paper_2006_03372_amd", "csrc", "khc_bfs.hip")
+    if vals.get("source_sha256:") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+        return None
+    return float(vals["traffic_bytes_per_launch:"])
+
+
 def cpu_baseline(g, h, budget_s=15.0, seed=0):
     """The oracle's scalar bounded BFS on a bounded random sample of the
     sources, single thread: traversed edges per second."""
@@ -59,6 +80,10 @@ def main():
     ap.add_argument("--h", type=int, default=3)
     ap.add_argument("--width", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--profile-pass", action="store_true",
+                    help="one untimed-warmup-free step without the work count or CPU leg, for profilers")
+    ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
+                    help="only run a plain device copy of MIB MiB three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
@@ -69,6 +94,18 @@ def main():
     import torch
     from paper_2006_03372_amd import khcore, synth
 
+    if args.calibrate_copy:
+        nbytes = args.calibrate_copy << 20
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration_copy_bytes": nbytes, "copies": 3}))
+        return
+    if args.profile_pass:
+        args.warmup, args.steps, args.no_cpu = 0, 1, True
+
     t = time.time()
     g = synth.rmat(args.scale, args.edge_factor, seed=1)
     log(f"generated R-MAT scale {args.scale} ef {args.edge_factor}: n={g.n} edges={g.num_edges} "
@@ -78,11 +115,13 @@ def main():
     gr = ctx.graph(g)
     h = args.h
 
-    te = ctx.scanned_arcs(gr, h)
-    torch.cuda.synchronize()
-    te_total = int(te.cpu().numpy().view(np.uint64).sum())
-    del te
-    log(f"traversed-edge total at h={h}: {te_total:.4e}")
+    te_total = 0
+    if not args.profile_pass:
+        te = ctx.scanned_arcs(gr, h)
+        torch.cuda.synchronize()
+        te_total = int(te.cpu().numpy().view(np.uint64).sum())
+        del te
+        log(f"traversed-edge total at h={h}: {te_total:.4e}")
 
     for i in range(args.warmup):
         ctx.hdeg(gr, h)
@@ -107,10 +146,16 @@ def main():
     avg_ms = last["ms"] / max(last["launches"], 1)
     avg_bytes = last["bytes"] / max(last["launches"], 1)
     achieved = avg_bytes / (avg_ms / 1e3) / 1e9
+    traffic = profiled_traffic() if (args.scale, args.edge_factor, h, args.width) == (20, 16, 3, 32) else None
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4), "traffic": None,
+                "frac": round(achieved / HBM_PEAK_GBS, 4),
+                "traffic": None if traffic is None else round(traffic / 1e9, 3),
+                "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
                 "kernel": f"level_kernel<W,LAST> (counting level), {last['launches']} launches, "
-                          f"avg {avg_ms:.3f} ms, {avg_bytes / 1e9:.3f} GB algorithmic per launch"}
+                          f"avg {avg_ms:.3f} ms, {avg_bytes / 1e9:.3f} GB algorithmic per launch"
+                          + ("" if traffic is None else
+                             f"; rocprof FETCH+WRITE {traffic / 1e9:.3f} GB per launch = "
+                             f"{traffic / (avg_ms / 1e3) / 1e9:.0f} GB/s")}
 
     result = {
         "metric": METRIC, "value": round(gteps, 2), "unit": "GTEPS", "n_gpus": 1,
