@@ -120,6 +120,7 @@ enum WsSlot {
     WS_QPTRS,
     WS_TE,
     WS_HQUEUE,
+    WS_DIRTY,
     WS_NUM_SLOTS
 };
 
