@@ -84,6 +84,12 @@ const char *khc_last_error(const khc_ctx *ctx);
 #define KHC_OPT_VALIDATE 4        /* 1 = validate the CSR in khc_graph_create (default 1)               */
 #define KHC_OPT_WAVES_PER_CU 5    /* wavefronts per CU for the BFS level kernels (4..32; default 16)     */
 #define KHC_OPT_PROFILE 6         /* 1 = time every BFS kernel launch with HIP events (default 0)       */
+#define KHC_OPT_DRIVER 7          /* decomposition driver: 0 = host loop over rounds, 1 = one persistent
+                                     kernel captured in a hipGraph (default 1)                        */
+#define KHC_OPT_PERSIST_WIDTH 8   /* uint64 words per vertex per BFS batch in the persistent driver
+                                     (8, 16 or 32; default 32)                                        */
+#define KHC_OPT_BARRIER_TIMEOUT 9 /* seconds a grid-barrier wait may take before the persistent kernel
+                                     aborts with KHC_EHIP (default 20)                                */
 int khc_set_option(khc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while KHC_OPT_PROFILE is 1, per kernel class:
@@ -109,6 +115,26 @@ int khc_profile_read(khc_ctx *ctx, khc_profile *out, int reset);
  * that is not simple and undirected gives KHC_EGRAPH.  Synchronous. */
 int khc_graph_create(khc_ctx *ctx, const khc_csr *g, khc_graph **out);
 int khc_graph_destroy(khc_graph *g);
+
+/* Several independent graphs packed together (batched decomposition).
+ * Graph g owns vertices [vtx_base[g], vtx_base[g+1]) of the concatenated
+ * arrays; its rows keep graph-LOCAL column ids.
+ *   G         number of graphs, >= 1
+ *   vtx_base  device uint64[G+1]: vtx_base[0] = 0, non-decreasing,
+ *             vtx_base[G] = total vertices (< 2^32 - 1)
+ *   row_ptr   device uint64[total + 1]: offsets into col (absolute)
+ *   col       device uint32[nnz]: graph-local ids 0..n_g-1, each graph a
+ *             simple undirected graph (validated as a whole when validation
+ *             is on; an id outside its own graph gives KHC_EGRAPH)
+ * The handle holds its own union column array (global ids) and a graph id
+ * per vertex; the caller's row_ptr must stay valid until khc_graph_destroy,
+ * col may be released after the call.  khcore_decompose on such a handle
+ * gives every vertex the core number it has in its own graph (core numbers
+ * of a disjoint union are per component) and, as removal round, the round
+ * of its own graph's peeling: all graphs advance one round per step of one
+ * persistent kernel.  Synchronous. */
+int khc_graph_create_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base, const uint64_t *row_ptr,
+                             const uint32_t *col, uint64_t nnz, khc_graph **out);
 
 /* Validate a CSR without keeping it: 0 or KHC_EGRAPH (message says why). */
 int khc_validate_csr(khc_ctx *ctx, const khc_csr *g);
@@ -152,6 +178,16 @@ int khdeg_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, u
  * Synchronous (reads a few scalars per round). */
 int khcore_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,
                      uint32_t *peel_round, khc_stats *stats);
+
+/* Batched (k,h)-core decomposition: khc_graph_create_batched, then
+ * khcore_decompose, then khc_graph_destroy (the "batched persistent" mode:
+ * all graphs run in one persistent kernel captured in a hipGraph).
+ *   core   device uint32[total vertices] output, vertex order of the input
+ *   peel_round, stats  as in khcore_decompose
+ * Synchronous. */
+int khcore_decompose_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base, const uint64_t *row_ptr,
+                             const uint32_t *col, uint64_t nnz, uint32_t h, uint32_t *core,
+                             uint32_t *peel_round, khc_stats *stats);
 
 #ifdef __cplusplus
 }

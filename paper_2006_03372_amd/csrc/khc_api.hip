@@ -66,6 +66,8 @@ int ws_get(khc_ctx *ctx, int slot, size_t bytes, void **out) {
                                                   " > " + std::to_string(ctx->ws_limit) + " bytes)");
     }
     if (b.ptr) {
+        // captured persistent launches hold the old address
+        drop_persist_graphs(ctx, nullptr);
         hipError_t e = hipStreamSynchronize(ctx->stream);
         if (e != hipSuccess) return check_hip(ctx, e, "stream sync before workspace growth");
         (void)hipFree(b.ptr);
@@ -236,6 +238,9 @@ int upload(khc_ctx *ctx, const std::vector<T> &v, T **out) {
 }
 
 }  // namespace
+
+int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out);
+
 }  // namespace khc
 
 using namespace khc;
@@ -258,6 +263,10 @@ int khc_create(khc_ctx **out, int device, void *hip_stream) {
     c->bufs.resize(WS_NUM_SLOTS);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    int rate_khz = 0;
+    if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate_khz > 0)
+        c->wall_clock_khz = (uint64_t)rate_khz;
+    (void)hipGetLastError();
     if (hipHostMalloc((void **)&c->host_scalars, 256, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return KHC_ENOMEM;
@@ -270,6 +279,7 @@ int khc_destroy(khc_ctx *ctx) {
     if (!ctx) return KHC_EINVAL;
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
+    drop_persist_graphs(ctx, nullptr);
     for (auto &b : ctx->bufs)
         if (b.ptr) (void)hipFree(b.ptr);
     for (auto &r : ctx->prof_pending) {
@@ -312,6 +322,19 @@ int khc_set_option(khc_ctx *ctx, int option, int64_t value) {
             return KHC_OK;
         case KHC_OPT_PROFILE:
             ctx->profile = value ? 1 : 0;
+            return KHC_OK;
+        case KHC_OPT_DRIVER:
+            if (value != 0 && value != 1) return set_error(ctx, KHC_EINVAL, "driver must be 0 or 1");
+            ctx->driver = (int)value;
+            return KHC_OK;
+        case KHC_OPT_PERSIST_WIDTH:
+            if (value != 8 && value != 16 && value != 32)
+                return set_error(ctx, KHC_EINVAL, "persistent width must be 8, 16 or 32 words");
+            ctx->persist_width = (int)value;
+            return KHC_OK;
+        case KHC_OPT_BARRIER_TIMEOUT:
+            if (value < 1 || value > 600) return set_error(ctx, KHC_EINVAL, "barrier timeout must be 1..600 s");
+            ctx->barrier_timeout_s = (int)value;
             return KHC_OK;
         default:
             return set_error(ctx, KHC_EINVAL, "unknown option " + std::to_string(option));
@@ -357,6 +380,139 @@ int khc_graph_create(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
     *out = nullptr;
     if (ctx->sticky) return set_error(ctx, KHC_EHIP, "context has a sticky HIP error");
     (void)hipSetDevice(ctx->device);
+    return graph_create_impl(ctx, g, out);
+}
+
+}  // extern "C"
+
+namespace khc {
+namespace {
+
+__global__ void graph_id_kernel(uint32_t n, uint32_t G, const uint64_t *vtx_base, uint32_t *gid) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        uint32_t lo = 0, hi = G;  // last g with vtx_base[g] <= v
+        while (hi - lo > 1) {
+            const uint32_t mid = lo + (hi - lo) / 2;
+            if (vtx_base[mid] <= v) lo = mid; else hi = mid;
+        }
+        gid[v] = lo;
+    }
+}
+
+// Local ids to global ids; an id outside its own graph sets flag bit 2.
+__global__ void union_col_kernel(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                                 const uint32_t *gid, const uint64_t *vtx_base, uint32_t *out,
+                                 uint32_t *flags) {
+    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
+        const uint32_t g = gid[v];
+        const uint64_t base = vtx_base[g], ng = vtx_base[g + 1] - base;
+        for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
+            const uint32_t c = col[e];
+            if (c >= ng) {
+                atomicOr(flags, 2u);
+                out[e] = 0;
+            } else {
+                out[e] = (uint32_t)(base + c);
+            }
+        }
+    }
+}
+
+}  // namespace
+}  // namespace khc
+
+extern "C" {
+
+int khc_graph_create_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base, const uint64_t *row_ptr,
+                             const uint32_t *col, uint64_t nnz, khc_graph **out) {
+    if (!ctx) return KHC_EINVAL;
+    if (!out) return set_error(ctx, KHC_EINVAL, "out is null");
+    *out = nullptr;
+    if (ctx->sticky) return set_error(ctx, KHC_EHIP, "context has a sticky HIP error");
+    if (G == 0 || !vtx_base || !row_ptr || (nnz && !col))
+        return set_error(ctx, KHC_EINVAL, "batched graph: G == 0 or null pointer");
+    (void)hipSetDevice(ctx->device);
+    hipStream_t st = ctx->stream;
+    std::vector<uint64_t> vb(G + 1);
+    hipError_t e = hipMemcpyAsync(vb.data(), vtx_base, (G + 1) * 8, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(ctx, e, "vtx_base download");
+    if (vb[0] != 0) return set_error(ctx, KHC_EINVAL, "vtx_base[0] must be 0");
+    for (uint32_t g = 0; g < G; ++g)
+        if (vb[g + 1] < vb[g]) return set_error(ctx, KHC_EINVAL, "vtx_base must be non-decreasing");
+    if (vb[G] >= 0xFFFFFFFFull) return set_error(ctx, KHC_EINVAL, "too many vertices in the batch");
+    const uint32_t n = (uint32_t)vb[G];
+    uint32_t *gid = nullptr, *ucol = nullptr, *flags = nullptr;
+    uint64_t *vbd = nullptr;
+    auto cleanup = [&]() {
+        if (gid) (void)hipFree(gid);
+        if (ucol) (void)hipFree(ucol);
+        if (vbd) (void)hipFree(vbd);
+    };
+    if (hipMalloc(&gid, (size_t)n * 4 + 4) != hipSuccess || hipMalloc(&ucol, nnz * 4 + 4) != hipSuccess ||
+        hipMalloc(&vbd, (G + 1) * 8) != hipSuccess) {
+        (void)hipGetLastError();
+        cleanup();
+        return set_error(ctx, KHC_ENOMEM, "batched graph allocation failed");
+    }
+    int rc;
+    void *fl;
+    if ((rc = ws_get(ctx, WS_FLAGS, 64, &fl))) {
+        cleanup();
+        return rc;
+    }
+    flags = (uint32_t *)fl;
+    e = hipMemcpyAsync(vbd, vtx_base, (G + 1) * 8, hipMemcpyDeviceToDevice, st);
+    if (e != hipSuccess) {
+        cleanup();
+        return check_hip(ctx, e, "vtx_base copy");
+    }
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, flags, 0u, (uint64_t)1);
+    const int grid = grid_for(n, 256, ctx->num_cu * 8);
+    hipLaunchKernelGGL(graph_id_kernel, dim3(grid), dim3(256), 0, st, n, G, (const uint64_t *)vbd, gid);
+    hipLaunchKernelGGL(union_col_kernel, dim3(grid), dim3(256), 0, st, n, row_ptr, col, gid,
+                       (const uint64_t *)vbd, ucol, flags);
+    uint32_t hf = 0;
+    e = hipMemcpyAsync(&hf, flags, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) {
+        cleanup();
+        return check_hip(ctx, e, "batched graph build");
+    }
+    if (hf & 2u) {
+        cleanup();
+        return set_error(ctx, KHC_EGRAPH, "batched graph: a column id lies outside its own graph");
+    }
+    khc_csr u{n, nnz, row_ptr, ucol};
+    khc_graph *gr = nullptr;
+    if ((rc = graph_create_impl(ctx, &u, &gr))) {
+        cleanup();
+        return rc;
+    }
+    gr->ngraphs = G;
+    gr->gid = gid;
+    gr->col_owned = ucol;
+    gr->vtx_base = vbd;
+    *out = gr;
+    return KHC_OK;
+}
+
+int khcore_decompose_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base, const uint64_t *row_ptr,
+                             const uint32_t *col, uint64_t nnz, uint32_t h, uint32_t *core,
+                             uint32_t *peel_round, khc_stats *stats) {
+    khc_graph *g = nullptr;
+    int rc = khc_graph_create_batched(ctx, G, vtx_base, row_ptr, col, nnz, &g);
+    if (rc) return rc;
+    rc = khcore_decompose(ctx, g, h, core, peel_round, stats);
+    khc_graph_destroy(g);
+    return rc;
+}
+
+}  // extern "C"
+
+namespace khc {
+
+int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
     int rc = check_csr_args(ctx, g);
     if (rc) return rc;
     if (ctx->validate && (rc = validate_impl(ctx, g))) return rc;
@@ -419,9 +575,19 @@ int khc_graph_create(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
     return KHC_OK;
 }
 
+}  // namespace khc
+
+extern "C" {
+
 int khc_graph_destroy(khc_graph *g) {
     if (!g) return KHC_EINVAL;
-    if (g->ctx) (void)hipStreamSynchronize(g->ctx->stream);
+    if (g->ctx) {
+        (void)hipStreamSynchronize(g->ctx->stream);
+        drop_persist_graphs(g->ctx, g);
+    }
+    if (g->gid) (void)hipFree(g->gid);
+    if (g->col_owned) (void)hipFree(g->col_owned);
+    if (g->vtx_base) (void)hipFree(g->vtx_base);
     if (g->light_rows) (void)hipFree(g->light_rows);
     if (g->heavy_rows) (void)hipFree(g->heavy_rows);
     if (g->chunk_heavy) (void)hipFree(g->chunk_heavy);

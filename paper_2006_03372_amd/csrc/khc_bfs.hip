@@ -1,520 +1,18 @@
-// Multi-source h-bounded BFS for h-degrees (gfx950).
-//
-// The h-degree d_v^h(G(S)) (Section II) of many sources is computed at once:
-// one batch carries 64*W sources as bit lanes of W uint64 words per vertex.
-// For every vertex y, vis[y] holds the lanes whose source has reached y and
-// frt[y] the lanes that reached y at the previous hop.  One level of the
-// bounded BFS is, for every live y,
-//     new[y] = (OR over live neighbours x of frt[x]) AND NOT vis[y]
-//     vis[y] |= new[y];  frt'[y] = new[y]
-// and d^h(source of lane l) = sum over the h levels of the number of rows
-// whose new[] has bit l set.  This transposes the paper's bitmap idea
-// (Section IV-B: bit j of a vertex's bitmap marks reachability of the j-th
-// vertex) -- here a bit marks a source lane, so one wide OR advances 64*W
-// bounded BFS runs by one hop.
-//
-// Each level runs in one of two directions, chosen on the device from the
-// size of the frontier (the total degree of the rows put on it by the
-// previous level):
-//  * pull: every live row gathers the frontier words of its neighbours.
-//    Rows up to kHeavyRowArcs arcs are handled by one group of W/2 lanes
-//    (16-byte loads; rows sorted by degree so a wavefront's rows are
-//    alike); heavier rows are cut into chunks of kChunkArcs arcs that whole
-//    workgroups OR together, the last chunk to finish completing the row.
-//  * push: every frontier row ORs its non-zero words into its live
-//    neighbours with atomics; the atomic's old value tells which bits are
-//    new, so each (row, lane) is counted once.
-// Workgroups are persistent and take work items from an atomic counter.
-// Frontier rows of each level are also kept as a list, which drives the
-// push direction and lets the batch clean up exactly the rows it touched:
-// between batches vis and the three frontier buffers are all zero.
-#include "khc_internal.h"
+// Host-driven multi-source bounded BFS (gfx950): h-degrees of a list of
+// sources in batches of 64*W, one kernel launch per BFS level.  The level
+// itself is lvl::level_body (khc_level.h).
+#include "khc_level.h"
 
 namespace khc {
 
 namespace {
 
-struct alignas(16) U2 {
-    uint64_t a, b;
-};
-
-template <int WPL>
-__device__ __forceinline__ void load_words(const uint64_t *p, uint64_t (&w)[WPL]) {
-    if constexpr (WPL == 2) {
-        U2 v = *reinterpret_cast<const U2 *>(p);
-        w[0] = v.a;
-        w[1] = v.b;
-    } else {
-        w[0] = *p;
-    }
-}
-
-template <int WPL>
-__device__ __forceinline__ void store_words(uint64_t *p, const uint64_t (&w)[WPL]) {
-    if constexpr (WPL == 2) {
-        U2 v;
-        v.a = w[0];
-        v.b = w[1];
-        *reinterpret_cast<U2 *>(p) = v;
-    } else {
-        *p = w[0];
-    }
-}
-
-constexpr int kPlanes = 8;            // bit-sliced per-lane counters hold up to 255
-constexpr int kUnroll = 8;            // independent gathers in flight per lane
-constexpr int kPushFactor = 16;       // push when frontier arcs * factor < all arcs
-constexpr int kGrab = 4;              // push work grab: one frontier item per wavefront
-constexpr uint32_t kPushChunk = 256;  // arcs per push item of a heavy frontier row
-constexpr int kStage = 1024;          // LDS staging of frontier rows (pull levels)
-
-// Frontier list of one level: every row once (q, count, total degree) and,
-// for rows with more than kPushChunk arcs, one push item per kPushChunk arcs
-// (row | chunk << 32) so heavy rows spread over many wavefronts.
-struct Frontier {
-    uint32_t *q;
-    uint32_t *qcnt;
-    unsigned long long *qdeg;
-    uint64_t *hq;
-    uint32_t *hcnt;
-};
-
-struct LevelParams {
-    const uint64_t *row_ptr;
-    const uint32_t *col;
-    const uint8_t *alive;
-    const uint32_t *light_rows;
-    const uint32_t *heavy_rows;
-    const uint32_t *chunk_heavy;
-    const uint32_t *chunk_first;
-    const uint64_t *frt_in;  // frontier of the previous level
-    uint64_t *frt_out;       // frontier of this level (all zero on entry)
-    uint64_t *frt_clr;       // buffer whose rows of q_clr are cleared here
-    uint64_t *vis;
-    const uint32_t *q_in;   // rows of the previous frontier
-    const uint64_t *hq_in;  // push items of its heavy rows
-    const uint32_t *qcnt_in;
-    const uint32_t *hcnt_in;
-    const unsigned long long *qdeg_in;
-    Frontier out;           // this level's frontier
-    const uint32_t *q_clr;  // rows of the frontier two levels back
-    const uint32_t *qcnt_clr;
-    uint32_t *fnz_out;  // 1 bit per vertex: row is on this level's frontier
-    uint32_t *fnz_clr;
-    uint64_t *hacc;
-    uint32_t *hdone;
-    uint32_t *work;    // work-item counter of this level
-    uint32_t *counts;  // per-lane reached-vertex totals, summed over levels
-    uint64_t nnz;
-    uint32_t n;
-    uint32_t n_light;
-    uint32_t n_chunks;
-};
-
-// Add the WPL words of x to the bit-sliced counters (one ripple-carry add
-// per word: plane k holds bit k of every bit position's count).
-template <int WPL>
-__device__ __forceinline__ void planes_add(uint64_t (&pl)[WPL][kPlanes], const uint64_t (&x)[WPL]) {
-#pragma unroll
-    for (int j = 0; j < WPL; ++j) {
-        uint64_t c = x[j];
-#pragma unroll
-        for (int k = 0; k < kPlanes; ++k) {
-            uint64_t t = pl[j][k] & c;
-            pl[j][k] ^= c;
-            c = t;
-        }
-    }
-}
-
-template <int WPL>
-__device__ __forceinline__ void planes_flush(uint64_t (&pl)[WPL][kPlanes], uint32_t *s_counts,
-                                             int word0) {
-#pragma unroll
-    for (int j = 0; j < WPL; ++j) {
-        uint64_t any = 0;
-#pragma unroll
-        for (int k = 0; k < kPlanes; ++k) any |= pl[j][k];
-        while (any) {
-            int b = __builtin_ctzll(any);
-            any &= any - 1;
-            uint32_t c = 0;
-#pragma unroll
-            for (int k = 0; k < kPlanes; ++k) c |= (uint32_t)((pl[j][k] >> b) & 1u) << k;
-            atomicAdd(&s_counts[(word0 + j) * 64 + b], c);
-        }
-#pragma unroll
-        for (int k = 0; k < kPlanes; ++k) pl[j][k] = 0;
-    }
-}
-
-__device__ __forceinline__ void count_word_bits(uint32_t *s_counts, int word, uint64_t bits) {
-    while (bits) {
-        int b = __builtin_ctzll(bits);
-        bits &= bits - 1;
-        atomicAdd(&s_counts[word * 64 + b], 1u);
-    }
-}
-
-// Push items of a heavy frontier row (called by the lane that lists it).
-__device__ __forceinline__ void add_push_items(const Frontier &f, uint32_t y, uint64_t dy) {
-    if (dy <= kPushChunk) return;
-    const uint32_t nch = (uint32_t)((dy + kPushChunk - 1) / kPushChunk);
-    const uint32_t at = atomicAdd(f.hcnt, nch);
-    for (uint32_t c = 0; c < nch; ++c) f.hq[at + c] = (uint64_t)y | ((uint64_t)c << 32);
-}
-
-// Wave-aggregated append straight to the global frontier list.  Must be
-// reached by every lane of the wavefront.
-__device__ __forceinline__ void append_direct(bool take, uint32_t y, uint64_t dy, const Frontier &f) {
-    const uint64_t m = __ballot(take);
-    if (!m) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __builtin_ctzll(m);
-    uint64_t dsum = take ? dy : 0;
-    for (int off = 32; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off, 64);
-    uint32_t base = 0;
-    if (lane == leader) {
-        base = atomicAdd(f.qcnt, (uint32_t)__builtin_popcountll(m));
-        atomicAdd(f.qdeg, (unsigned long long)dsum);
-    }
-    base = __shfl(base, leader, 64);
-    if (take) {
-        f.q[base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = y;
-        add_push_items(f, y, dy);
-    }
-}
-
-// Wave-aggregated append to the workgroup's LDS staging list.
-__device__ __forceinline__ void append_staged(bool take, uint32_t y, uint32_t *s_stage,
-                                              uint32_t *s_sn) {
-    const uint64_t m = __ballot(take);
-    if (!m) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __builtin_ctzll(m);
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(s_sn, (uint32_t)__builtin_popcountll(m));
-    base = __shfl(base, leader, 64);
-    if (take) s_stage[base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = y;
-}
-
-// Move the staged rows to the global frontier list (whole workgroup; one
-// pair of global atomics per flush).
-__device__ void flush_staged(const Frontier &f, const uint64_t *row_ptr, uint32_t *s_stage,
-                             uint32_t *s_sn, uint32_t *s_base, unsigned long long *s_deg) {
-    __syncthreads();
-    const uint32_t cnt = *s_sn;
-    if (cnt == 0) return;
-    if (threadIdx.x == 0) {
-        *s_base = atomicAdd(f.qcnt, cnt);
-        *s_deg = 0;
-    }
-    __syncthreads();
-    const uint32_t base = *s_base;
-    uint64_t dsum = 0;
-    for (uint32_t i = threadIdx.x; i < cnt; i += blockDim.x) {
-        const uint32_t y = s_stage[i];
-        const uint64_t dy = row_ptr[y + 1] - row_ptr[y];
-        f.q[base + i] = y;
-        add_push_items(f, y, dy);
-        dsum += dy;
-    }
-    for (int off = 32; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off, 64);
-    if ((threadIdx.x & 63) == 0 && dsum) atomicAdd(s_deg, (unsigned long long)dsum);
-    __syncthreads();
-    if (threadIdx.x == 0) {
-        atomicAdd(f.qdeg, *s_deg);
-        *s_sn = 0;
-    }
-    __syncthreads();
-}
-
-// Push one frontier row x over its arcs [ab, ae): OR its non-zero words
-// into live neighbours; bits the atomic shows as new are counted and put
-// on this level's frontier.  One wavefront, lanes over (arc, word) pairs.
-template <int W, bool LAST>
-__device__ void push_range(const LevelParams &p, uint32_t x, uint64_t ab, uint64_t ae,
-                           uint32_t *s_counts) {
-    const int lane = threadIdx.x & 63;
-    const uint64_t myw = lane < W ? p.frt_in[(size_t)x * W + lane] : 0ull;
-    const uint64_t nzmask = __ballot(myw != 0);
-    const uint32_t nz = (uint32_t)__builtin_popcountll(nzmask);
-    const uint64_t pairs = (ae - ab) * nz;
-    for (uint64_t base = 0; base < pairs; base += 64) {
-        const uint64_t pr = base + lane;
-        bool take = false;
-        uint32_t y = 0;
-        uint64_t dy = 0;
-        if (pr < pairs) {
-            const uint64_t arc = pr / nz;
-            uint32_t k = (uint32_t)(pr - arc * nz);
-            uint64_t mm = nzmask;
-            for (; k > 0; --k) mm &= mm - 1;  // k-th set bit
-            const int w = __builtin_ctzll(mm);
-            y = p.col[ab + arc];
-            if (!p.alive || p.alive[y]) {
-                const uint64_t bits = p.frt_in[(size_t)x * W + w];
-                uint64_t *vp = p.vis + (size_t)y * W + w;
-                const uint64_t nb = bits & ~*vp;
-                if (nb) {
-                    const uint64_t tn =
-                        nb & ~(uint64_t)atomicOr((unsigned long long *)vp, (unsigned long long)nb);
-                    if (tn) {
-                        count_word_bits(s_counts, w, tn);
-                        if constexpr (!LAST)
-                            atomicOr((unsigned long long *)(p.frt_out + (size_t)y * W + w),
-                                     (unsigned long long)tn);
-                        const uint32_t ybit = 1u << (y & 31);
-                        if (!(atomicOr(&p.fnz_out[y >> 5], ybit) & ybit)) {
-                            take = true;
-                            dy = p.row_ptr[y + 1] - p.row_ptr[y];
-                        }
-                    }
-                }
-            }
-        }
-        append_direct(take, y, dy, p.out);
-    }
-}
+using namespace lvl;
 
 template <int W, bool LAST>
 __global__ __launch_bounds__(kBlockThreads) void level_kernel(LevelParams p) {
-    using L = RowLayout<W>;
-    constexpr int WPL = L::WPL, LPR = L::LPR, RPW = L::RPW, GROUPS = L::GROUPS;
-    // light rows handled per work item: several passes of all lane groups
-    constexpr int PASSES = GROUPS >= 64 ? 1 : 64 / GROUPS;
-    __shared__ uint64_t s_red[GROUPS * W];
-    __shared__ uint64_t s_fin[W];
-    __shared__ uint32_t s_counts[64 * W];
-    __shared__ uint32_t s_stage[LAST ? 1 : kStage];
-    __shared__ uint32_t s_sn, s_base, s_item, s_flag;
-    __shared__ unsigned long long s_deg;
-
-    const int tid = threadIdx.x;
-    const int lane = tid & 63;
-    const int wave = tid >> 6;
-    const int lig = lane % LPR;  // lane within its row group
-    const int group = wave * RPW + lane / LPR;
-    const size_t gstride = (size_t)gridDim.x * kBlockThreads;
-    const size_t gtid = (size_t)blockIdx.x * kBlockThreads + tid;
-
-    // Clear the rows of the frontier two levels back: its buffer and map
-    // are written by the next level.
-    if (p.q_clr) {
-        const uint32_t nclr = *p.qcnt_clr;
-        for (size_t i = gtid; i < (size_t)nclr * W; i += gstride) {
-            const uint32_t y = p.q_clr[i / W];
-            p.frt_clr[(size_t)y * W + (i % W)] = 0;
-        }
-        for (size_t i = gtid; i < nclr; i += gstride) p.fnz_clr[p.q_clr[i] >> 5] = 0;
-    }
-
-    for (int i = tid; i < 64 * W; i += kBlockThreads) s_counts[i] = 0;
-    if (tid == 0) s_sn = 0;
-    uint64_t pl[WPL][kPlanes];
-#pragma unroll
-    for (int j = 0; j < WPL; ++j)
-#pragma unroll
-        for (int k = 0; k < kPlanes; ++k) pl[j][k] = 0;
-    uint32_t pcount = 0;
-
-    const bool push = (unsigned long long)(*p.qdeg_in) * kPushFactor < (unsigned long long)p.nnz;
-    const uint32_t qn_in = *p.qcnt_in;
-    const uint32_t hn_in = *p.hcnt_in;
-    const uint32_t light_grabs = (qn_in + kGrab - 1) / kGrab;
-    const uint32_t n_items = push ? light_grabs + (hn_in + kGrab - 1) / kGrab
-                                  : p.n_chunks + (p.n_light + GROUPS * PASSES - 1) / (GROUPS * PASSES);
-    __syncthreads();
-
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(p.work, 1u);
-        __syncthreads();
-        const uint32_t item = s_item;
-        if (item >= n_items) break;
-
-        if (push) {
-            // ---- push: one frontier item per wavefront ----
-            if (item < light_grabs) {
-                const uint32_t qi = item * kGrab + wave;
-                if (qi < qn_in) {
-                    const uint32_t x = p.q_in[qi];
-                    const uint64_t rb = p.row_ptr[x], re = p.row_ptr[x + 1];
-                    if (re - rb <= kPushChunk) push_range<W, LAST>(p, x, rb, re, s_counts);
-                }
-            } else {
-                const uint32_t hi = (item - light_grabs) * kGrab + wave;
-                if (hi < hn_in) {
-                    const uint64_t it = p.hq_in[hi];
-                    const uint32_t x = (uint32_t)it;
-                    const uint64_t rb = p.row_ptr[x], re = p.row_ptr[x + 1];
-                    const uint64_t ab = rb + (it >> 32) * kPushChunk;
-                    const uint64_t ae = ab + kPushChunk < re ? ab + kPushChunk : re;
-                    push_range<W, LAST>(p, x, ab, ae, s_counts);
-                }
-            }
-        } else if (item < p.n_chunks) {
-            // ---- pull, one chunk of a heavy row, whole workgroup ----
-            const uint32_t hi = p.chunk_heavy[item];
-            const uint32_t y = p.heavy_rows[hi];
-            const bool live = !p.alive || p.alive[y];
-            if (live) {
-                const uint32_t c0 = p.chunk_first[hi];
-                const uint32_t nch = p.chunk_first[hi + 1] - c0;
-                const uint64_t rb = p.row_ptr[y], re = p.row_ptr[y + 1];
-                const uint64_t b = rb + (uint64_t)(item - c0) * kChunkArcs;
-                const uint64_t e = (b + kChunkArcs < re) ? b + kChunkArcs : re;
-                uint64_t acc[WPL];
-#pragma unroll
-                for (int j = 0; j < WPL; ++j) acc[j] = 0;
-                uint64_t a = b + group;
-                for (; a + (uint64_t)(kUnroll - 1) * GROUPS < e; a += (uint64_t)kUnroll * GROUPS) {
-                    uint32_t xs[kUnroll];
-#pragma unroll
-                    for (int u = 0; u < kUnroll; ++u) xs[u] = p.col[a + (uint64_t)u * GROUPS];
-                    uint64_t t[kUnroll][WPL];
-#pragma unroll
-                    for (int u = 0; u < kUnroll; ++u)
-                        load_words<WPL>(p.frt_in + (size_t)xs[u] * W + lig * WPL, t[u]);
-#pragma unroll
-                    for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-                        for (int j = 0; j < WPL; ++j) acc[j] |= t[u][j];
-                }
-                for (; a < e; a += GROUPS) {
-                    uint64_t t[WPL];
-                    load_words<WPL>(p.frt_in + (size_t)p.col[a] * W + lig * WPL, t);
-#pragma unroll
-                    for (int j = 0; j < WPL; ++j) acc[j] |= t[j];
-                }
-#pragma unroll
-                for (int j = 0; j < WPL; ++j) s_red[group * W + lig * WPL + j] = acc[j];
-                __syncthreads();
-                if (tid < W) {
-                    uint64_t r = 0;
-                    for (int g = 0; g < GROUPS; ++g) r |= s_red[g * W + tid];
-                    s_fin[tid] = r;
-                }
-                __syncthreads();
-                bool finalize = true;
-                if (nch > 1) {
-                    if (tid < W && s_fin[tid])
-                        atomicOr((unsigned long long *)&p.hacc[(size_t)hi * W + tid],
-                                 (unsigned long long)s_fin[tid]);
-                    __threadfence();
-                    __syncthreads();
-                    if (tid == 0) s_flag = (atomicAdd(&p.hdone[hi], 1u) == nch - 1) ? 1u : 0u;
-                    __syncthreads();
-                    finalize = s_flag != 0;
-                    if (finalize) {
-                        __threadfence();
-                        if (tid < W)
-                            s_fin[tid] = atomicExch((unsigned long long *)&p.hacc[(size_t)hi * W + tid], 0ull);
-                        if (tid == 0) atomicExch(&p.hdone[hi], 0u);
-                        __syncthreads();
-                    }
-                }
-                if (finalize && tid < 64) {
-                    // wave 0 completes the row: lane t < W owns word t
-                    uint64_t nw = 0;
-                    if (tid < W) {
-                        const uint64_t v = p.vis[(size_t)y * W + tid];
-                        nw = s_fin[tid] & ~v;
-                        if (nw) {
-                            count_word_bits(s_counts, tid, nw);
-                            if constexpr (!LAST) {
-                                p.frt_out[(size_t)y * W + tid] = nw;
-                                p.vis[(size_t)y * W + tid] = v | nw;
-                            }
-                        }
-                    }
-                    if constexpr (!LAST) {
-                        const bool any = __ballot(nw != 0) != 0;
-                        if (tid == 0 && any) atomicOr(&p.fnz_out[y >> 5], 1u << (y & 31));
-                        append_staged(tid == 0 && any, y, s_stage, &s_sn);
-                    }
-                }
-            }
-        } else {
-            // ---- pull, light rows: one lane group per row ----
-            const uint32_t tile = item - p.n_chunks;
-            for (int pass = 0; pass < PASSES; ++pass) {
-                const uint32_t idx = (tile * PASSES + pass) * GROUPS + group;
-                bool valid = idx < p.n_light;
-                const uint32_t y = valid ? p.light_rows[idx] : 0u;
-                if (valid && p.alive && !p.alive[y]) valid = false;
-                uint64_t acc[WPL];
-#pragma unroll
-                for (int j = 0; j < WPL; ++j) acc[j] = 0;
-                if (valid) {
-                    const uint64_t rb = p.row_ptr[y], re = p.row_ptr[y + 1];
-                    uint64_t a = rb;
-                    for (; a + kUnroll <= re; a += kUnroll) {
-                        uint32_t xs[kUnroll];
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u) xs[u] = p.col[a + u];
-                        uint64_t t[kUnroll][WPL];
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u)
-                            load_words<WPL>(p.frt_in + (size_t)xs[u] * W + lig * WPL, t[u]);
-#pragma unroll
-                        for (int u = 0; u < kUnroll; ++u)
-#pragma unroll
-                            for (int j = 0; j < WPL; ++j) acc[j] |= t[u][j];
-                    }
-                    for (; a < re; ++a) {
-                        uint64_t t[WPL];
-                        load_words<WPL>(p.frt_in + (size_t)p.col[a] * W + lig * WPL, t);
-#pragma unroll
-                        for (int j = 0; j < WPL; ++j) acc[j] |= t[j];
-                    }
-                }
-                uint64_t v[WPL], nw[WPL];
-                if (valid) {
-                    load_words<WPL>(p.vis + (size_t)y * W + lig * WPL, v);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < WPL; ++j) v[j] = ~0ull;
-                }
-                uint64_t any = 0;
-#pragma unroll
-                for (int j = 0; j < WPL; ++j) {
-                    nw[j] = acc[j] & ~v[j];
-                    any |= nw[j];
-                }
-                planes_add<WPL>(pl, nw);
-                if (++pcount == (1u << kPlanes) - 1u) {
-                    planes_flush<WPL>(pl, s_counts, lig * WPL);
-                    pcount = 0;
-                }
-                if constexpr (!LAST) {
-                    if (any) {
-                        uint64_t vv[WPL];
-#pragma unroll
-                        for (int j = 0; j < WPL; ++j) vv[j] = v[j] | nw[j];
-                        store_words<WPL>(p.frt_out + (size_t)y * W + lig * WPL, nw);
-                        store_words<WPL>(p.vis + (size_t)y * W + lig * WPL, vv);
-                    }
-                    const uint64_t m = __ballot(any != 0);
-                    const uint64_t gmask = (LPR == 64) ? ~0ull : ((1ull << LPR) - 1ull);
-                    const int gshift = (lane / LPR) * LPR;
-                    const bool lead = valid && lig == 0 && ((m >> gshift) & gmask);
-                    if (lead) atomicOr(&p.fnz_out[y >> 5], 1u << (y & 31));
-                    append_staged(lead, y, s_stage, &s_sn);
-                }
-            }
-        }
-        __syncthreads();
-        if constexpr (!LAST) {
-            // at most 256 rows are staged per work item
-            if (s_sn > kStage - 256) flush_staged(p.out, p.row_ptr, s_stage, &s_sn, &s_base, &s_deg);
-        }
-    }
-
-    if constexpr (!LAST) flush_staged(p.out, p.row_ptr, s_stage, &s_sn, &s_base, &s_deg);
-    planes_flush<WPL>(pl, s_counts, lig * WPL);
-    __syncthreads();
-    for (int i = tid; i < 64 * W; i += kBlockThreads)
-        if (s_counts[i]) atomicAdd(&p.counts[i], s_counts[i]);
+    __shared__ LevelLds<W> sh;
+    level_body<W, LAST>(p, sh);
 }
 
 // Reset the per-batch counters: level work counters, frontier list sizes

@@ -66,6 +66,23 @@ struct khc_ctx {
     std::vector<ProfRec> prof_pending;
     std::vector<hipEvent_t> prof_pool;
     khc_profile prof_acc{};
+    // persistent driver
+    int driver = 1;             // 0 host-driven rounds, 1 one persistent kernel
+    int persist_width = 32;     // source words per BFS batch in the persistent kernel
+    int barrier_timeout_s = 20; // deadline of one grid-barrier wait
+    uint64_t wall_clock_khz = 100000;
+    struct PersistGraph {
+        const khc_graph *g;
+        uint32_t h;
+        int W, grid, bounded;
+        uint32_t *core, *round;
+        hipGraphExec_t exec;
+        bool same_args(const PersistGraph &o) const {
+            return g == o.g && h == o.h && W == o.W && grid == o.grid && bounded == o.bounded &&
+                   core == o.core && round == o.round;
+        }
+    };
+    std::vector<PersistGraph> persist_graphs;
 };
 
 struct khc_graph {
@@ -83,6 +100,11 @@ struct khc_graph {
     uint32_t *chunk_first = nullptr;  // first chunk of each heavy row [n_heavy + 1]
     uint32_t n_chunks = 0;
     uint32_t max_degree = 0;
+    // several graphs packed as one disjoint union: gid[v] = graph of v
+    uint32_t ngraphs = 1;
+    uint32_t *gid = nullptr;       // device, owned (null: one graph)
+    uint32_t *col_owned = nullptr; // device, owned union column ids (batched graphs)
+    uint64_t *vtx_base = nullptr;  // device, owned copy of the graph offsets [ngraphs + 1]
 };
 
 namespace khc {
@@ -121,6 +143,10 @@ enum WsSlot {
     WS_TE,
     WS_HQUEUE,
     WS_DIRTY,
+    WS_GRAPHK,
+    WS_AHQ,
+    WS_CTL,
+    WS_SYNC,
     WS_NUM_SLOTS
 };
 
@@ -135,5 +161,14 @@ int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
 // over the vertices within h-1 hops of s, s included).  Asynchronous.
 int msbfs_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                        const uint32_t *srcs, uint32_t nsrc, uint64_t *te_full);
+
+// Whole decomposition in one persistent kernel (khc_persist.hip).
+int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,
+                         uint32_t *peel_round, khc_stats *stats);
+// Host-driven decomposition (khc_peel.hip).
+int host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core, uint32_t *peel_round,
+                   khc_stats *stats);
+// Forget captured persistent launches (their arguments are stale).
+void drop_persist_graphs(khc_ctx *ctx, const khc_graph *only);
 
 }  // namespace khc

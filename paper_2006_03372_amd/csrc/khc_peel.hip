@@ -254,13 +254,10 @@ int peel_round_common(khc_ctx *ctx, const khc_graph *g, uint32_t h, const PeelSt
 
 }  // namespace
 
-extern "C" int khcore_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,
-                                uint32_t *peel_round, khc_stats *stats) {
-    if (!ctx) return KHC_EINVAL;
-    if (ctx->sticky) return set_error(ctx, KHC_EHIP, "context has a sticky HIP error");
-    if (!g || !core) return set_error(ctx, KHC_EINVAL, "graph or output is null");
-    if (h == 0) return set_error(ctx, KHC_EINVAL, "h must be >= 1");
-    (void)hipSetDevice(ctx->device);
+int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,
+                        uint32_t *peel_round, khc_stats *stats) {
+    if (g->ngraphs > 1)
+        return set_error(ctx, KHC_EINVAL, "graphs packed together need the persistent driver");
     const auto t0 = std::chrono::steady_clock::now();
     khc_stats st_local;
     std::memset(&st_local, 0, sizeof(st_local));

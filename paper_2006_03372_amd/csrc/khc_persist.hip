@@ -1,0 +1,798 @@
+// Device-resident (k,h)-core peeling: one persistent kernel runs the whole
+// decomposition (gfx950).
+//
+// The host-driven driver (khc_peel.hip) pays a kernel launch per step and a
+// host round trip per round; peeling needs hundreds to tens of thousands of
+// rounds, most of them small.  Here every step is a phase of one persistent
+// kernel whose workgroups are all resident (grid sized from the occupancy
+// of this kernel), and phases are separated by grid barriers.  Each barrier
+// wait has a wall-clock deadline: a wait that exceeds it raises an abort
+// flag that every workgroup checks, so the kernel always exits.  The launch
+// is captured once in a hipGraph and replayed.
+//
+// The algorithm is the bounded schedule of khc_peel.hip (or the plain one):
+// levels k <- max(k, min key), dirty vertices whose lower bound reaches the
+// level are recomputed first, P = {clean live v : d(v) <= k} is removed, the
+// vertices within h hops of P in the graph before removal are found by a
+// push BFS, exact (h-1)-degrees are recomputed within h-1 hops of P, and the
+// vertices within h hops of P become dirty with fresh lower bounds.
+//
+// Several graphs can be decomposed together: their disjoint union is one
+// CSR and gid[v] names the graph of v.  Each graph keeps its own level
+// K[g]; every step removes, in every graph that still has vertices, the
+// vertices at or below that graph's level, so a graph's removal rounds are
+// the steps and each graph's core numbers are exactly its own (core numbers
+// of a disjoint union are per component).  Sources of different graphs
+// share BFS batches: the graphs are disjoint, so their lanes never meet.
+#include <chrono>
+#include <cstring>
+
+#include "khc_level.h"
+
+namespace khc {
+namespace {
+
+using namespace lvl;
+
+constexpr int kMaxPersistH = 32;
+constexpr uint32_t kAffChunk = 1024;  // arcs per work item of a heavy affected-BFS row
+
+struct PCtl {
+    unsigned long long left;  // live vertices
+    uint32_t rn;              // dirty vertices to recompute
+    uint32_t round;
+    uint32_t nsrc;            // initial sources (live vertices with a live neighbour)
+    uint32_t abort_reason;
+    uint32_t acnt[kMaxPersistH + 2];   // affected BFS: rows appended per level (0: P)
+    uint32_t ahcnt[kMaxPersistH + 2];  // heavy-row work items per level
+    unsigned long long stat_hrec, stat_hm1, stat_aff, stat_batches;
+};
+
+struct Sync {
+    uint32_t *count;
+    uint32_t *gen;
+    uint32_t *abort;
+    uint32_t nblocks;
+    uint64_t timeout_ticks;
+};
+
+struct PParams {
+    const uint64_t *row_ptr;
+    const uint32_t *col;
+    uint64_t nnz;
+    uint32_t n;
+    uint32_t n_light, n_chunks;
+    const uint32_t *light_rows, *heavy_rows, *chunk_heavy, *chunk_first;
+    const uint32_t *gid;  // graph of each vertex (null: one graph)
+    uint32_t ngraphs;
+    uint32_t h;
+    int bounded;
+    // peeling state
+    uint8_t *alive, *dirty;
+    uint32_t *d, *dm, *lb, *mark, *queue, *list, *core, *round;
+    uint32_t *K, *MIN;
+    uint64_t *ahq;  // affected BFS heavy items, per level
+    size_t ahq_len;
+    PCtl *ctl;
+    // BFS workspace
+    uint64_t *vis;
+    uint64_t *frt0, *frt1, *frt2;
+    uint32_t *fnz;
+    uint32_t fnz_words;
+    uint64_t *hacc;
+    uint32_t *hdone;
+    uint32_t *counts;
+    uint32_t *bq;   // frontier lists, n entries per level
+    uint64_t *bhq;  // push items, hq_len per level
+    size_t hq_len;
+    uint32_t *bqcnt, *bhcnt, *bwork;
+    unsigned long long *bqdeg;
+    Sync sync;
+};
+
+// Grid barrier.  Thread 0 of each workgroup arrives with an atomic; the
+// last arrival resets the count and bumps the generation.  Waiters poll the
+// generation with a deadline and the abort flag.  Returns false if the
+// kernel must exit.
+__device__ bool grid_sync(const Sync &s, uint32_t *s_gen, uint32_t *s_ok) {
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        const uint32_t g = *s_gen;
+        uint32_t ok = 1;
+        __threadfence();
+        if (atomicAdd(s.count, 1u) == s.nblocks - 1) {
+            atomicExch(s.count, 0u);
+            __threadfence();
+            atomicAdd(s.gen, 1u);
+        } else {
+            const uint64_t t0 = wall_clock64();
+            while (__hip_atomic_load(s.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+                if (__hip_atomic_load(s.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
+                    ok = 0;
+                    break;
+                }
+                if (wall_clock64() - t0 > s.timeout_ticks) {
+                    atomicExch(s.abort, 1u);
+                    ok = 0;
+                    break;
+                }
+                __builtin_amdgcn_s_sleep(1);
+            }
+        }
+        __threadfence();
+        if (__hip_atomic_load(s.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
+        *s_gen = g + 1;
+        *s_ok = ok;
+    }
+    __syncthreads();
+    return *s_ok != 0;
+}
+
+__device__ __forceinline__ uint32_t graph_of(const PParams &p, uint32_t v) { return p.gid ? p.gid[v] : 0u; }
+
+__device__ __forceinline__ size_t gtid() { return (size_t)blockIdx.x * blockDim.x + threadIdx.x; }
+__device__ __forceinline__ size_t gstride() { return (size_t)gridDim.x * blockDim.x; }
+
+// Wave-aggregated append of `take` lanes' values to list[base + ...].
+__device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *list, uint32_t *counter,
+                                            uint32_t offset) {
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(m);
+    uint32_t base = 0;
+    if (lane == leader) base = atomicAdd(counter, (uint32_t)__builtin_popcountll(m));
+    base = __shfl(base, leader, 64);
+    if (take) list[offset + base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = v;
+}
+
+__device__ __forceinline__ uint64_t *frt_buf(const PParams &p, uint32_t i) {
+    return i == 0 ? p.frt0 : (i == 1 ? p.frt1 : p.frt2);
+}
+
+// lb(u) = max(dm(u), max over live neighbours of dm); one wavefront per u.
+__device__ void lower_bounds(const PParams &p, const uint32_t *list, uint32_t begin, uint32_t end,
+                             bool mark_dirty) {
+    const int lane = threadIdx.x & 63;
+    const size_t wave = gtid() >> 6, nwaves = gstride() >> 6;
+    for (size_t i = begin + wave; i < end; i += nwaves) {
+        const uint32_t u = list ? list[i] : (uint32_t)i;
+        if (!p.alive[u]) continue;
+        uint32_t m = 0;
+        for (uint64_t a = p.row_ptr[u] + lane; a < p.row_ptr[u + 1]; a += 64) {
+            const uint32_t w = p.col[a];
+            if (p.alive[w] && p.dm[w] > m) m = p.dm[w];
+        }
+        for (int off = 32; off > 0; off >>= 1) {
+            const uint32_t o = __shfl_xor(m, off, 64);
+            m = o > m ? o : m;
+        }
+        if (lane == 0) {
+            p.lb[u] = p.dm[u] > m ? p.dm[u] : m;
+            if (mark_dirty) p.dirty[u] = 1;
+        }
+    }
+}
+
+// Work items of a heavy row in the affected BFS (rows of the next level).
+__device__ __forceinline__ void add_aff_items(const PParams &p, uint32_t level, uint32_t y) {
+    const uint64_t dy = p.row_ptr[y + 1] - p.row_ptr[y];
+    if (dy <= kAffChunk) return;
+    const uint32_t nch = (uint32_t)((dy + kAffChunk - 1) / kAffChunk);
+    const uint32_t at = atomicAdd(&p.ctl->ahcnt[level], nch);
+    uint64_t *items = p.ahq + (size_t)level * p.ahq_len;
+    for (uint32_t c = 0; c < nch; ++c) items[at + c] = (uint64_t)y | ((uint64_t)c << 32);
+}
+
+// One level of the affected-set BFS (push from the previous level's rows,
+// one wavefront per row or per kAffChunk arcs of a heavy row).
+__device__ void affected_level(const PParams &p, uint32_t L) {
+    uint32_t e_prev2 = 0, e_prev = 0;  // queue[e_prev2, e_prev) is level L-1
+    for (uint32_t j = 0; j + 1 < L; ++j) e_prev2 += p.ctl->acnt[j];
+    e_prev = e_prev2 + p.ctl->acnt[L - 1];
+    const uint32_t nh = p.ctl->ahcnt[L - 1];
+    const uint64_t *items = p.ahq + (size_t)(L - 1) * p.ahq_len;
+    const uint32_t nl = e_prev - e_prev2;
+    const int lane = threadIdx.x & 63;
+    const size_t wave = gtid() >> 6, nwaves = gstride() >> 6;
+    for (size_t it = wave; it < (size_t)nl + nh; it += nwaves) {
+        uint32_t x;
+        uint64_t ab, ae;
+        if (it < nl) {
+            x = p.queue[e_prev2 + it];
+            ab = p.row_ptr[x];
+            ae = p.row_ptr[x + 1];
+            if (ae - ab > kAffChunk) continue;  // covered by its work items
+        } else {
+            const uint64_t v = items[it - nl];
+            x = (uint32_t)v;
+            ab = p.row_ptr[x] + (v >> 32) * kAffChunk;
+            const uint64_t re = p.row_ptr[x + 1];
+            ae = ab + kAffChunk < re ? ab + kAffChunk : re;
+        }
+        for (uint64_t a0 = ab; a0 < ae; a0 += 64) {
+            const uint64_t a = a0 + lane;
+            bool take = false;
+            uint32_t y = 0;
+            if (a < ae) {
+                y = p.col[a];
+                take = p.alive[y] && p.mark[y] == 0u && atomicCAS(&p.mark[y], 0u, 1u) == 0u;
+            }
+            const uint64_t m = __ballot(take);
+            if (m) {
+                const int leader = __builtin_ctzll(m);
+                uint32_t base = 0;
+                if (lane == leader) base = atomicAdd(&p.ctl->acnt[L], (uint32_t)__builtin_popcountll(m));
+                base = __shfl(base, leader, 64);
+                if (take) {
+                    p.queue[e_prev + base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = y;
+                    if (L < p.h) add_aff_items(p, L, y);
+                }
+            }
+        }
+    }
+}
+
+// Phases of the persistent kernel.  Every workgroup runs the same phase,
+// then a grid barrier, then computes the next phase from values written
+// before that barrier, so all workgroups follow the same sequence.
+enum Phase : int {
+    PH_INIT,
+    PH_COMPACT,
+    PH_LB_ALL,
+    PH_KEYMIN,
+    PH_LEVEL,
+    PH_COLLECT,
+    PH_CLEAN,
+    PH_SELECT,
+    PH_AFF,
+    PH_KILL,
+    PH_LBD,      // lower bounds and dirtiness of the affected set, unmark
+    PH_UNMARK,
+    PH_BFS_RESET,
+    PH_BFS_SEED,
+    PH_BFS_LEVEL,
+    PH_BFS_SCATTER,
+    PH_DONE
+};
+
+// A bounded-BFS job: h-degrees (levels hops) of srcs[0..n) into out[], then
+// continue with phase ret.
+struct Job {
+    const uint32_t *srcs;
+    uint32_t n, levels;
+    uint32_t *out;
+    int ret;
+};
+
+template <int W>
+__global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams p) {
+    __shared__ LevelLds<W> sh;
+    __shared__ uint32_t s_gen, s_ok;
+    if (threadIdx.x == 0) s_gen = 0;
+    const uint32_t n = p.n, h = p.h;
+    const bool bounded = p.bounded != 0;
+    PCtl *ctl = p.ctl;
+    const uint32_t per = 64u * W;
+    const int lane = threadIdx.x & 63;
+
+    // uniform control state
+    int phase = PH_INIT;
+    Job job{nullptr, 0, 0, nullptr, PH_DONE};
+    uint32_t batch = 0, lev = 0, aff_l = 0, np = 0, e_hm1 = 0, e_h = 0;
+    auto start_job = [&](const uint32_t *srcs, uint32_t cnt, uint32_t levels, uint32_t *out, int ret) {
+        job = Job{srcs, cnt, levels, out, ret};
+        batch = 0;
+        return cnt ? (int)PH_BFS_RESET : ret;
+    };
+
+    for (;;) {
+        // ------------------------------------------------------------ work
+        switch (phase) {
+            case PH_INIT:
+                for (size_t v = gtid(); v < n; v += gstride()) {
+                    p.alive[v] = 1;
+                    p.dirty[v] = 0;
+                    p.mark[v] = 0;
+                    p.core[v] = 0;
+                    if (p.round) p.round[v] = 0;
+                    p.d[v] = 0;
+                    p.dm[v] = 0;
+                }
+                for (size_t g = gtid(); g < p.ngraphs; g += gstride()) {
+                    p.K[g] = 0;
+                    p.MIN[g] = 0xFFFFFFFFu;
+                }
+                if (gtid() == 0) {
+                    ctl->left = n;
+                    ctl->rn = 0;
+                    ctl->round = 0;
+                    ctl->nsrc = 0;
+                    ctl->abort_reason = 0;
+                    for (int i = 0; i < kMaxPersistH + 2; ++i) ctl->acnt[i] = ctl->ahcnt[i] = 0;
+                    ctl->stat_hrec = ctl->stat_hm1 = ctl->stat_aff = ctl->stat_batches = 0;
+                }
+                break;
+            case PH_COMPACT:
+                // sources of the initial degrees: vertices with a neighbour
+                for (size_t v0 = gtid() - lane; v0 < n; v0 += gstride()) {
+                    const size_t v = v0 + lane;
+                    const bool take = v < n && p.row_ptr[v + 1] > p.row_ptr[v];
+                    wave_append(take, (uint32_t)v, p.list, &ctl->nsrc, 0);
+                }
+                if (gtid() == 0) {
+                    ctl->stat_hrec += n;
+                    if (bounded) ctl->stat_hm1 += n;
+                }
+                break;
+            case PH_LB_ALL:
+                lower_bounds(p, nullptr, 0, n, false);
+                break;
+            case PH_KEYMIN:
+                for (size_t v = gtid(); v < n; v += gstride()) {
+                    if (!p.alive[v]) continue;
+                    const uint32_t key = (bounded && p.dirty[v]) ? p.lb[v] : p.d[v];
+                    const uint32_t g = graph_of(p, (uint32_t)v);
+                    if (key < p.MIN[g]) atomicMin(&p.MIN[g], key);
+                }
+                break;
+            case PH_LEVEL:
+                for (size_t g = gtid(); g < p.ngraphs; g += gstride()) {
+                    const uint32_t m = p.MIN[g];
+                    if (m != 0xFFFFFFFFu && m > p.K[g]) p.K[g] = m;
+                    p.MIN[g] = 0xFFFFFFFFu;
+                }
+                if (gtid() == 0) {
+                    ctl->rn = 0;
+                    for (int i = 0; i < kMaxPersistH + 2; ++i) ctl->acnt[i] = ctl->ahcnt[i] = 0;
+                }
+                break;
+            case PH_COLLECT:
+                // dirty vertices whose lower bound reached their graph's level
+                for (size_t v0 = gtid() - lane; v0 < n; v0 += gstride()) {
+                    const size_t v = v0 + lane;
+                    const bool take =
+                        v < n && p.alive[v] && p.dirty[v] && p.lb[v] <= p.K[graph_of(p, (uint32_t)v)];
+                    wave_append(take, (uint32_t)v, p.list, &ctl->rn, 0);
+                }
+                break;
+            case PH_CLEAN: {
+                const uint32_t rn = ctl->rn;
+                for (size_t i = gtid(); i < rn; i += gstride()) p.dirty[p.list[i]] = 0;
+                if (gtid() == 0) ctl->stat_hrec += rn;
+                break;
+            }
+            case PH_SELECT: {
+                // P: clean live vertices at or below their graph's level
+                const uint32_t r = ctl->round;
+                for (size_t v0 = gtid() - lane; v0 < n; v0 += gstride()) {
+                    const size_t v = v0 + lane;
+                    bool take = false;
+                    if (v < n && p.alive[v] && !(bounded && p.dirty[v])) {
+                        const uint32_t k = p.K[graph_of(p, (uint32_t)v)];
+                        if (p.d[v] <= k) {
+                            take = true;
+                            p.core[v] = k;
+                            if (p.round) p.round[v] = r;
+                            p.mark[v] = 1;
+                        }
+                    }
+                    const uint64_t m = __ballot(take);
+                    if (m) {
+                        const int leader = __builtin_ctzll(m);
+                        uint32_t base = 0;
+                        if (lane == leader) base = atomicAdd(&ctl->acnt[0], (uint32_t)__builtin_popcountll(m));
+                        base = __shfl(base, leader, 64);
+                        if (take) {
+                            p.queue[base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = (uint32_t)v;
+                            add_aff_items(p, 0, (uint32_t)v);
+                        }
+                    }
+                }
+                break;
+            }
+            case PH_AFF:
+                affected_level(p, aff_l);
+                break;
+            case PH_KILL: {
+                np = ctl->acnt[0];
+                e_hm1 = e_h = 0;
+                for (uint32_t j = 0; j <= h; ++j) {
+                    if (j < h) e_hm1 += ctl->acnt[j];
+                    e_h += ctl->acnt[j];
+                }
+                for (size_t i = gtid(); i < np; i += gstride()) p.alive[p.queue[i]] = 0;
+                if (gtid() == 0) {
+                    ctl->left -= np;
+                    ctl->round += 1;
+                    ctl->stat_aff += e_h - np;
+                    if (bounded) ctl->stat_hm1 += e_hm1 - np;
+                    else ctl->stat_hrec += e_h - np;
+                    if (np == 0) {
+                        ctl->abort_reason = 1;
+                        atomicExch(p.sync.abort, 1u);
+                    }
+                }
+                break;
+            }
+            case PH_LBD:
+                lower_bounds(p, p.queue, np, e_h, true);
+                for (size_t i = gtid(); i < e_h; i += gstride()) p.mark[p.queue[i]] = 0;
+                break;
+            case PH_UNMARK:
+                for (size_t i = gtid(); i < e_h; i += gstride()) p.mark[p.queue[i]] = 0;
+                break;
+            case PH_BFS_RESET:
+                if (blockIdx.x == 0) {
+                    for (uint32_t i = threadIdx.x; i <= job.levels; i += blockDim.x) {
+                        p.bwork[i] = 0;
+                        p.bqcnt[i] = 0;
+                        p.bhcnt[i] = 0;
+                        p.bqdeg[i] = 0;
+                    }
+                    for (uint32_t i = threadIdx.x; i < per; i += blockDim.x) p.counts[i] = 0;
+                    if (threadIdx.x == 0) ctl->stat_batches++;
+                }
+                break;
+            case PH_BFS_SEED: {
+                // lane l of the batch on its source, level-0 list entry l
+                const uint32_t first = batch * per;
+                const uint32_t cnt = job.n - first < per ? job.n - first : per;
+                Frontier f0;
+                f0.q = p.bq;
+                f0.qcnt = p.bqcnt;
+                f0.qdeg = p.bqdeg;
+                f0.hq = p.bhq;
+                f0.hcnt = p.bhcnt;
+                for (size_t l = gtid(); l < cnt; l += gstride()) {
+                    const uint32_t s = job.srcs[first + l];
+                    f0.q[l] = s;
+                    if (!p.alive[s]) continue;
+                    const uint64_t bit = 1ull << (l & 63);
+                    p.vis[(size_t)s * W + (l >> 6)] |= bit;
+                    p.frt0[(size_t)s * W + (l >> 6)] |= bit;
+                    atomicOr(&p.fnz[s >> 5], 1u << (s & 31));
+                    const uint64_t ds = p.row_ptr[s + 1] - p.row_ptr[s];
+                    atomicAdd(f0.qdeg, (unsigned long long)ds);
+                    add_push_items(f0, s, ds);
+                }
+                if (gtid() == 0) *f0.qcnt = cnt;
+                break;
+            }
+            case PH_BFS_LEVEL: {
+                LevelParams lp;
+                lp.row_ptr = p.row_ptr;
+                lp.col = p.col;
+                lp.alive = p.alive;
+                lp.light_rows = p.light_rows;
+                lp.heavy_rows = p.heavy_rows;
+                lp.chunk_heavy = p.chunk_heavy;
+                lp.chunk_first = p.chunk_first;
+                lp.frt_in = frt_buf(p, (lev - 1) % 3);
+                lp.frt_out = frt_buf(p, lev % 3);
+                lp.frt_clr = frt_buf(p, (lev + 1) % 3);
+                lp.vis = p.vis;
+                lp.q_in = p.bq + (size_t)(lev - 1) * n;
+                lp.hq_in = p.bhq + (size_t)(lev - 1) * p.hq_len;
+                lp.qcnt_in = p.bqcnt + lev - 1;
+                lp.hcnt_in = p.bhcnt + lev - 1;
+                lp.qdeg_in = p.bqdeg + lev - 1;
+                lp.out.q = p.bq + (size_t)lev * n;
+                lp.out.qcnt = p.bqcnt + lev;
+                lp.out.qdeg = p.bqdeg + lev;
+                lp.out.hq = p.bhq + (size_t)lev * p.hq_len;
+                lp.out.hcnt = p.bhcnt + lev;
+                lp.q_clr = lev >= 2 ? p.bq + (size_t)(lev - 2) * n : nullptr;
+                lp.qcnt_clr = lev >= 2 ? p.bqcnt + lev - 2 : nullptr;
+                lp.fnz_out = p.fnz + (size_t)(lev % 3) * p.fnz_words;
+                lp.fnz_clr = p.fnz + (size_t)((lev + 1) % 3) * p.fnz_words;
+                lp.hacc = p.hacc;
+                lp.hdone = p.hdone;
+                lp.work = p.bwork + lev;
+                lp.counts = p.counts;
+                lp.nnz = p.nnz;
+                lp.n = n;
+                lp.n_light = p.n_light;
+                lp.n_chunks = p.n_chunks;
+                if (lev == job.levels)
+                    level_body<W, true>(lp, sh);
+                else
+                    level_body<W, false>(lp, sh);
+                break;
+            }
+            case PH_BFS_SCATTER: {
+                // results, then clear what the batch touched
+                const uint32_t first = batch * per;
+                const uint32_t cnt = job.n - first < per ? job.n - first : per;
+                for (size_t l = gtid(); l < cnt; l += gstride()) job.out[job.srcs[first + l]] = p.counts[l];
+                for (uint32_t j = 0; j <= job.levels; ++j) {
+                    const uint32_t c = p.bqcnt[j];
+                    const uint32_t *q = p.bq + (size_t)j * n;
+                    for (size_t i = gtid(); i < (size_t)c * W; i += gstride())
+                        p.vis[(size_t)q[i / W] * W + (i % W)] = 0;
+                }
+                for (uint32_t j = job.levels - 1; j <= job.levels; ++j) {
+                    const uint32_t c = p.bqcnt[j];
+                    const uint32_t *q = p.bq + (size_t)j * n;
+                    uint64_t *buf = frt_buf(p, j % 3);
+                    uint32_t *fz = p.fnz + (size_t)(j % 3) * p.fnz_words;
+                    for (size_t i = gtid(); i < (size_t)c * W; i += gstride())
+                        buf[(size_t)q[i / W] * W + (i % W)] = 0;
+                    for (size_t i = gtid(); i < c; i += gstride()) fz[q[i] >> 5] = 0;
+                }
+                break;
+            }
+            default:
+                break;
+        }
+        if (!grid_sync(p.sync, &s_gen, &s_ok)) return;
+
+        // ------------------------------------------------------ next phase
+        switch (phase) {
+            case PH_INIT: phase = PH_COMPACT; break;
+            case PH_COMPACT:
+                phase = start_job(p.list, ctl->nsrc, h, p.d, bounded ? (int)PH_LB_ALL : (int)PH_KEYMIN);
+                // the (h-1)-degrees follow the h-degrees with the same sources
+                break;
+            case PH_LB_ALL: phase = ctl->left ? PH_KEYMIN : PH_DONE; break;
+            case PH_KEYMIN: phase = PH_LEVEL; break;
+            case PH_LEVEL: phase = bounded ? PH_COLLECT : PH_SELECT; break;
+            case PH_COLLECT: {
+                const uint32_t rn = ctl->rn;
+                phase = rn ? start_job(p.list, rn, h, p.d, PH_CLEAN) : (int)PH_SELECT;
+                break;
+            }
+            case PH_CLEAN: phase = PH_KEYMIN; break;
+            case PH_SELECT:
+                aff_l = 1;
+                phase = PH_AFF;
+                break;
+            case PH_AFF:
+                if (aff_l < h) ++aff_l;
+                else phase = PH_KILL;
+                break;
+            case PH_KILL:
+                if (bounded)
+                    phase = start_job(p.queue + np, e_hm1 - np, h - 1, p.dm, PH_LBD);
+                else
+                    phase = start_job(p.queue + np, e_h - np, h, p.d, PH_UNMARK);
+                break;
+            case PH_LBD:
+            case PH_UNMARK: phase = ctl->left ? PH_KEYMIN : PH_DONE; break;
+            case PH_BFS_RESET: phase = PH_BFS_SEED; break;
+            case PH_BFS_SEED:
+                lev = 1;
+                phase = PH_BFS_LEVEL;
+                break;
+            case PH_BFS_LEVEL:
+                if (lev < job.levels) ++lev;
+                else phase = PH_BFS_SCATTER;
+                break;
+            case PH_BFS_SCATTER:
+                if ((batch + 1) * per < job.n) {
+                    ++batch;
+                    phase = PH_BFS_RESET;
+                } else if (job.ret == PH_LB_ALL && job.levels == h && bounded) {
+                    // initial h-degrees done: now the initial (h-1)-degrees
+                    phase = start_job(p.list, ctl->nsrc, h - 1, p.dm, PH_LB_ALL);
+                } else {
+                    phase = job.ret;
+                    if (phase == PH_KEYMIN && !ctl->left) phase = PH_DONE;
+                }
+                break;
+            default: phase = PH_DONE; break;
+        }
+        if (phase == PH_DONE) return;
+    }
+}
+
+__global__ void sync_reset_kernel(uint32_t *count, uint32_t *gen, uint32_t *abort) {
+    *count = 0;
+    *gen = 0;
+    *abort = 0;
+}
+
+template <int W>
+int persistent_grid(khc_ctx *ctx) {
+    int per_cu = 0;
+    if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, peel_persistent_kernel<W>, kBlockThreads, 0) !=
+            hipSuccess ||
+        per_cu < 1) {
+        (void)hipGetLastError();
+        return -1;
+    }
+    const int want = (ctx->waves_per_cu + 3) / 4;
+    return ctx->num_cu * (want < per_cu ? want : per_cu);
+}
+
+template <int W>
+void launch_persistent(const PParams &p, int grid, hipStream_t st) {
+    hipLaunchKernelGGL(peel_persistent_kernel<W>, dim3(grid), dim3(kBlockThreads), 0, st, p);
+}
+
+}  // namespace
+
+// Runs the whole decomposition in one persistent kernel (captured in a
+// hipGraph and replayed for identical arguments).
+int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,
+                         uint32_t *peel_round, khc_stats *stats) {
+    if (h > (uint32_t)kMaxPersistH)
+        return set_error(ctx, KHC_EINVAL, "the persistent driver supports h <= 32");
+    const auto t0 = std::chrono::steady_clock::now();
+    const uint32_t n = g->n;
+    const int W = ctx->persist_width;
+    const bool bounded = ctx->schedule == 1 && h >= 2;
+    const uint32_t levels_max = h;
+    const uint32_t nq = levels_max + 1;
+    const size_t words = (size_t)n * W;
+    const uint32_t fnz_words = (n + 31) / 32;
+    const size_t hq_len = (size_t)n + g->nnz / 256 + 1;
+    const size_t ahq_len = (size_t)n + g->nnz / kAffChunk + 1;
+    void *vis, *f0, *f1, *f2, *fnz, *hacc, *hdone, *counts, *bq, *bhq, *bctr, *alive, *dirty, *d, *dm, *lb,
+        *mark, *queue, *list, *kg, *ming, *ahq, *ctl, *sync;
+    int rc;
+    if ((rc = ws_get(ctx, WS_VIS, words * 8, &vis)) || (rc = ws_get(ctx, WS_FRT0, words * 8, &f0)) ||
+        (rc = ws_get(ctx, WS_FRT1, words * 8, &f1)) || (rc = ws_get(ctx, WS_FRT2, words * 8, &f2)) ||
+        (rc = ws_get(ctx, WS_FNZ, (size_t)fnz_words * 3 * 4, &fnz)) ||
+        (rc = ws_get(ctx, WS_HACC, ((size_t)g->n_heavy + 1) * W * 8, &hacc)) ||
+        (rc = ws_get(ctx, WS_HDONE, ((size_t)g->n_heavy + 1) * 4, &hdone)) ||
+        (rc = ws_get(ctx, WS_COUNTS, (size_t)64 * kMaxWidth * 4, &counts)) ||
+        (rc = ws_get(ctx, WS_BQUEUE, (size_t)nq * n * 4 + 4, &bq)) ||
+        (rc = ws_get(ctx, WS_HQUEUE, (size_t)nq * hq_len * 8, &bhq)) ||
+        (rc = ws_get(ctx, WS_MISC, (size_t)nq * 24 + 64, &bctr)) ||
+        (rc = ws_get(ctx, WS_ALIVE, (size_t)n + 8, &alive)) ||
+        (rc = ws_get(ctx, WS_DIRTY, (size_t)n + 8, &dirty)) ||
+        (rc = ws_get(ctx, WS_DEG, (size_t)n * 4 + 8, &d)) ||
+        (rc = ws_get(ctx, WS_DHM1, (size_t)n * 4 + 8, &dm)) ||
+        (rc = ws_get(ctx, WS_LB, (size_t)n * 4 + 8, &lb)) ||
+        (rc = ws_get(ctx, WS_MARK, (size_t)n * 4 + 8, &mark)) ||
+        (rc = ws_get(ctx, WS_QUEUE0, (size_t)n * 4 + 8, &queue)) ||
+        (rc = ws_get(ctx, WS_QUEUE1, (size_t)n * 4 + 8, &list)) ||
+        (rc = ws_get(ctx, WS_GRAPHK, (size_t)g->ngraphs * 8 + 8, &kg)) ||
+        (rc = ws_get(ctx, WS_AHQ, (size_t)(h + 1) * ahq_len * 8, &ahq)) ||
+        (rc = ws_get(ctx, WS_CTL, sizeof(PCtl), &ctl)) ||
+        (rc = ws_get(ctx, WS_SYNC, 64, &sync)))
+        return rc;
+    ming = (uint32_t *)kg + g->ngraphs;
+    PParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.row_ptr = g->row_ptr;
+    p.col = g->col;
+    p.nnz = g->nnz;
+    p.n = n;
+    p.n_light = g->n_light;
+    p.n_chunks = g->n_chunks;
+    p.light_rows = g->light_rows;
+    p.heavy_rows = g->heavy_rows;
+    p.chunk_heavy = g->chunk_heavy;
+    p.chunk_first = g->chunk_first;
+    p.gid = g->gid;
+    p.ngraphs = g->ngraphs;
+    p.h = h;
+    p.bounded = bounded ? 1 : 0;
+    p.alive = (uint8_t *)alive;
+    p.dirty = (uint8_t *)dirty;
+    p.d = (uint32_t *)d;
+    p.dm = (uint32_t *)dm;
+    p.lb = (uint32_t *)lb;
+    p.mark = (uint32_t *)mark;
+    p.queue = (uint32_t *)queue;
+    p.list = (uint32_t *)list;
+    p.core = core;
+    p.round = peel_round;
+    p.K = (uint32_t *)kg;
+    p.MIN = (uint32_t *)ming;
+    p.ahq = (uint64_t *)ahq;
+    p.ahq_len = ahq_len;
+    p.ctl = (PCtl *)ctl;
+    p.vis = (uint64_t *)vis;
+    p.frt0 = (uint64_t *)f0;
+    p.frt1 = (uint64_t *)f1;
+    p.frt2 = (uint64_t *)f2;
+    p.fnz = (uint32_t *)fnz;
+    p.fnz_words = fnz_words;
+    p.hacc = (uint64_t *)hacc;
+    p.hdone = (uint32_t *)hdone;
+    p.counts = (uint32_t *)counts;
+    p.bq = (uint32_t *)bq;
+    p.bhq = (uint64_t *)bhq;
+    p.hq_len = hq_len;
+    p.bqdeg = (unsigned long long *)bctr;
+    p.bwork = (uint32_t *)(p.bqdeg + nq);
+    p.bqcnt = p.bwork + nq;
+    p.bhcnt = p.bqcnt + nq;
+    uint32_t *sp = (uint32_t *)sync;
+    p.sync.count = sp;
+    p.sync.gen = sp + 1;
+    p.sync.abort = sp + 2;
+    int grid = -1;
+    switch (W) {
+        case 8: grid = persistent_grid<8>(ctx); break;
+        case 16: grid = persistent_grid<16>(ctx); break;
+        default: grid = persistent_grid<32>(ctx); break;
+    }
+    if (grid < 1) return set_error(ctx, KHC_EHIP, "occupancy query for the persistent kernel failed");
+    p.sync.nblocks = (uint32_t)grid;
+    p.sync.timeout_ticks = (uint64_t)ctx->wall_clock_khz * 1000ull * (uint64_t)ctx->barrier_timeout_s;
+    hipStream_t st = ctx->stream;
+
+    // one graph per argument set, replayed on later calls
+    khc_ctx::PersistGraph key{g, h, W, grid, bounded ? 1 : 0, core, peel_round, nullptr};
+    hipGraphExec_t exec = nullptr;
+    for (auto &e : ctx->persist_graphs)
+        if (e.same_args(key)) exec = e.exec;
+    if (!exec) {
+        hipGraph_t graph;
+        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return check_hip(ctx, e, "graph capture begin");
+        hipLaunchKernelGGL(sync_reset_kernel, dim3(1), dim3(1), 0, st, p.sync.count, p.sync.gen, p.sync.abort);
+        switch (W) {
+            case 8: launch_persistent<8>(p, grid, st); break;
+            case 16: launch_persistent<16>(p, grid, st); break;
+            default: launch_persistent<32>(p, grid, st); break;
+        }
+        e = hipStreamEndCapture(st, &graph);
+        if (e != hipSuccess) return check_hip(ctx, e, "graph capture end");
+        e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
+        (void)hipGraphDestroy(graph);
+        if (e != hipSuccess) return check_hip(ctx, e, "graph instantiate");
+        key.exec = exec;
+        ctx->persist_graphs.push_back(key);
+    }
+    hipError_t e = hipGraphLaunch(exec, st);
+    if (e != hipSuccess) return check_hip(ctx, e, "graph launch");
+    PCtl host_ctl;
+    uint32_t host_sync[3];
+    e = hipMemcpyAsync(&host_ctl, ctl, sizeof(PCtl), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_sync, sync, 12, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(ctx, e, "persistent decomposition");
+    if (host_sync[2]) {
+        if (host_ctl.abort_reason == 1) return set_error(ctx, KHC_ELIMIT, "a round removed no vertex");
+        return set_error(ctx, KHC_EHIP, "persistent decomposition aborted: a grid barrier wait exceeded " +
+                                            std::to_string(ctx->barrier_timeout_s) + " s");
+    }
+    if (stats) {
+        std::memset(stats, 0, sizeof(*stats));
+        stats->rounds = host_ctl.round;
+        stats->h_recomputes = host_ctl.stat_hrec;
+        stats->hm1_recomputes = host_ctl.stat_hm1;
+        stats->bfs_batches = host_ctl.stat_batches;
+        stats->affected_total = host_ctl.stat_aff;
+        stats->width_words = (uint32_t)W;
+        stats->wall_ms =
+            std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
+    }
+    return KHC_OK;
+}
+
+void drop_persist_graphs(khc_ctx *ctx, const khc_graph *only) {
+    auto &v = ctx->persist_graphs;
+    for (size_t i = 0; i < v.size();) {
+        if (!only || v[i].g == only) {
+            (void)hipGraphExecDestroy(v[i].exec);
+            v.erase(v.begin() + i);
+        } else {
+            ++i;
+        }
+    }
+}
+
+}  // namespace khc
+
+using namespace khc;
+
+extern "C" int khcore_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,
+                                uint32_t *peel_round, khc_stats *stats) {
+    if (!ctx) return KHC_EINVAL;
+    if (ctx->sticky) return set_error(ctx, KHC_EHIP, "context has a sticky HIP error");
+    if (!g || !core) return set_error(ctx, KHC_EINVAL, "graph or output is null");
+    if (h == 0) return set_error(ctx, KHC_EINVAL, "h must be >= 1");
+    (void)hipSetDevice(ctx->device);
+    if (g->n == 0) {
+        if (stats) std::memset(stats, 0, sizeof(*stats));
+        return KHC_OK;
+    }
+    if (ctx->driver == 1 || g->ngraphs > 1) return persistent_decompose(ctx, g, h, core, peel_round, stats);
+    return host_decompose(ctx, g, h, core, peel_round, stats);
+}

@@ -27,11 +27,15 @@ OPT_WORKSPACE_LIMIT = 3
 OPT_VALIDATE = 4
 OPT_WAVES_PER_CU = 5
 OPT_PROFILE = 6
+OPT_DRIVER = 7
+OPT_PERSIST_WIDTH = 8
+OPT_BARRIER_TIMEOUT = 9
 
 EXPORTED = [
     "khc_create", "khc_destroy", "khc_last_error", "khc_set_option", "khc_profile_read",
     "khc_graph_create", "khc_graph_destroy", "khc_validate_csr",
     "khdeg_compute", "khdeg_compute_list", "khdeg_scanned_arcs", "khcore_decompose",
+    "khc_graph_create_batched", "khcore_decompose_batched",
 ]
 
 
@@ -94,6 +98,8 @@ def load_library(path: str = LIB_PATH):
         "khdeg_compute_list": ([P, P, P, u32, P, u32, P], i32),
         "khdeg_scanned_arcs": ([P, P, P, u32, P], i32),
         "khcore_decompose": ([P, P, u32, P, P, ctypes.POINTER(Stats)], i32),
+        "khc_graph_create_batched": ([P, u32, P, P, P, u64, PP], i32),
+        "khcore_decompose_batched": ([P, u32, P, P, P, u64, u32, P, P, ctypes.POINTER(Stats)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -163,6 +169,10 @@ class Context:
     def graph(self, g) -> "Graph":
         """Upload a host CSR (synth.CSR) and build its row schedule."""
         return Graph(self, g)
+
+    def batch(self, graphs) -> "BatchedGraph":
+        """Pack several host CSRs (synth.CSR) into one batched graph handle."""
+        return BatchedGraph(self, graphs)
 
     def validate(self, row_ptr, col, n: int) -> int:
         """Validate a device CSR; returns the status code (0 = ok)."""
@@ -236,3 +246,36 @@ class Graph:
             self.close()
         except Exception:
             pass
+
+
+class BatchedGraph(Graph):
+    """Several graphs packed together: concatenated rows, graph-local column
+    ids, vtx_base offsets; decomposed by one persistent kernel."""
+
+    def __init__(self, ctx: Context, graphs):
+        torch = _torch()
+        self.ctx = ctx
+        self.device = torch.device("cuda", ctx.device)
+        ns = [int(g.n) for g in graphs]
+        vb = np.zeros(len(graphs) + 1, dtype=np.uint64)
+        np.cumsum(ns, out=vb[1:])
+        arc_off = np.zeros(len(graphs) + 1, dtype=np.uint64)
+        np.cumsum([int(g.row_ptr[-1]) for g in graphs], out=arc_off[1:])
+        rp = np.concatenate([np.asarray(g.row_ptr[:-1], dtype=np.uint64) + arc_off[i]
+                             for i, g in enumerate(graphs)] + [arc_off[-1:]])
+        col = np.concatenate([np.asarray(g.col, dtype=np.uint32) for g in graphs])
+        self.n = int(vb[-1])
+        self.nnz = int(arc_off[-1])
+        self.vtx_base_host = vb
+        self.vtx_base = torch.from_numpy(vb.view(np.int64)).to(self.device)
+        self.row_ptr = torch.from_numpy(rp.view(np.int64)).to(self.device)
+        if col.size == 0:
+            col = np.zeros(1, dtype=np.uint32)
+        col_dev = torch.from_numpy(col.view(np.int32)).to(self.device)
+        h = ctypes.c_void_p()
+        ctx._check(ctx.lib.khc_graph_create_batched(ctx.handle, len(graphs), _dptr(self.vtx_base),
+                                                    _dptr(self.row_ptr), _dptr(col_dev), self.nnz,
+                                                    ctypes.byref(h)))
+        del col_dev
+        self.handle = h
+

@@ -1,0 +1,97 @@
+"""GPU parity of the batched decomposition (many graphs, one persistent
+kernel): every graph's core numbers and removal rounds equal the oracle's
+for that graph alone."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_2006_03372_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2006_03372_amd import khcore
+    c = khcore.Context(0)
+    c.set_option(khcore.OPT_BARRIER_TIMEOUT, 10)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _u32(t):
+    return t.cpu().numpy().view(np.uint32)
+
+
+def _graphs(count, lo, hi, seed):
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(lo, hi + 1, size=count)
+    ms = rng.uniform(3.0, 10.0, size=count)
+    return [synth.chung_lu(int(ns[i]), float(ms[i]), 2.5, seed * 1000 + i) for i in range(count)]
+
+
+def _run(ctx, graphs, h, schedule=1, width=16):
+    from paper_2006_03372_amd import khcore
+    ctx.set_option(khcore.OPT_SCHEDULE, schedule)
+    ctx.set_option(khcore.OPT_PERSIST_WIDTH, width)
+    b = ctx.batch(graphs)
+    c, r, st = ctx.core(b, h, with_round=True)
+    out = _u32(c), _u32(r), st, b.vtx_base_host
+    b.close()
+    return out
+
+
+@pytest.mark.parametrize("h", [2, 3])
+def test_batch_matches_oracle_per_graph(ctx, h):
+    graphs = _graphs(24, 30, 700, seed=5 + h)
+    graphs.append(synth.from_edges(7, [], []))          # isolated vertices only
+    graphs.append(synth.cycle(2 * h + 3))               # closed form: all 2h
+    graphs.insert(3, synth.complete(9))                 # closed form: all 8
+    for sched in (0, 1):
+        for width in (8, 32):
+            print(f"batch h={h} schedule={sched} width={width} graphs={len(graphs)}", flush=True)
+            c, r, st, vb = _run(ctx, graphs, h, sched, width)
+            for i, g in enumerate(graphs):
+                lo, hi = int(vb[i]), int(vb[i + 1])
+                c_ref, r_ref = oracle.peel(g, h)
+                assert (c[lo:hi] == c_ref).all(), (i, sched, width)
+                assert (r[lo:hi] == r_ref).all(), (i, sched, width)
+            assert st["rounds"] == max(int(oracle.peel(g, h)[1].max()) + 1 for g in graphs if g.n)
+
+
+def test_batch_equals_single_graph_runs(ctx):
+    from paper_2006_03372_amd import khcore
+    graphs = _graphs(12, 200, 3000, seed=11)
+    c, r, st, vb = _run(ctx, graphs, 3)
+    ctx.set_option(khcore.OPT_DRIVER, 1)
+    for i, g in enumerate(graphs):
+        gr = ctx.graph(g)
+        cs, rs, _ = ctx.core(gr, 3, with_round=True)
+        gr.close()
+        lo, hi = int(vb[i]), int(vb[i + 1])
+        assert (c[lo:hi] == _u32(cs)).all()
+        assert (r[lo:hi] == _u32(rs)).all()
+    # deterministic
+    c2, r2, _, _ = _run(ctx, graphs, 3)
+    assert (c == c2).all() and (r == r2).all()
+
+
+def test_batch_rejects_foreign_column(ctx):
+    import torch
+    from paper_2006_03372_amd import khcore
+    g0 = synth.path(4)
+    g1 = synth.path(3)
+    vb = torch.tensor([0, 4, 7], dtype=torch.int64, device="cuda")
+    rp = np.concatenate([g0.row_ptr[:-1], g1.row_ptr + g0.row_ptr[-1]]).astype(np.uint64)
+    col = np.concatenate([g0.col, g1.col]).astype(np.uint32)
+    col[0] = 5  # vertex 0 of graph 0 points outside graph 0
+    rpt = torch.from_numpy(rp.view(np.int64)).cuda()
+    ct = torch.from_numpy(col.view(np.int32)).cuda()
+    import ctypes
+    h = ctypes.c_void_p()
+    rc = ctx.lib.khc_graph_create_batched(ctx.handle, 2, ctypes.c_void_p(vb.data_ptr()),
+                                          ctypes.c_void_p(rpt.data_ptr()), ctypes.c_void_p(ct.data_ptr()),
+                                          int(rp[-1]), ctypes.byref(h))
+    assert rc == khcore.KHC_EGRAPH

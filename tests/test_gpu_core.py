@@ -27,10 +27,13 @@ def _u32(t):
     return t.cpu().numpy().view(np.uint32)
 
 
-def _gpu_core(ctx, g, h, schedule=1, width=16):
+def _gpu_core(ctx, g, h, schedule=1, width=16, driver=1):
     from paper_2006_03372_amd import khcore
     ctx.set_option(khcore.OPT_SCHEDULE, schedule)
     ctx.set_option(khcore.OPT_MAX_WIDTH, width)
+    ctx.set_option(khcore.OPT_DRIVER, driver)
+    ctx.set_option(khcore.OPT_PERSIST_WIDTH, max(width, 8))
+    ctx.set_option(khcore.OPT_BARRIER_TIMEOUT, 10)
     gr = ctx.graph(g)
     c, r, st = ctx.core(gr, h, with_round=True)
     out = _u32(c), _u32(r), st
@@ -38,14 +41,15 @@ def _gpu_core(ctx, g, h, schedule=1, width=16):
     return out
 
 
-def _check(ctx, g, h, schedules=(0, 1), widths=(16,)):
+def _check(ctx, g, h, schedules=(0, 1), widths=(16,), drivers=(0, 1)):
     c_ref, r_ref = oracle.peel(g, h)
-    for s in schedules:
-        for w in widths:
-            print(f"core n={g.n} nnz={g.nnz} h={h} schedule={s} width={w}", flush=True)
-            c, r, st = _gpu_core(ctx, g, h, s, w)
-            assert (c == c_ref).all(), (s, w, np.flatnonzero(c != c_ref)[:10])
-            assert (r == r_ref).all(), (s, w, np.flatnonzero(r != r_ref)[:10])
+    for drv in drivers:
+        for s in schedules:
+            for w in widths:
+                print(f"core n={g.n} nnz={g.nnz} h={h} driver={drv} schedule={s} width={w}", flush=True)
+                c, r, st = _gpu_core(ctx, g, h, s, w, drv)
+                assert (c == c_ref).all(), (drv, s, w, np.flatnonzero(c != c_ref)[:10])
+                assert (r == r_ref).all(), (drv, s, w, np.flatnonzero(r != r_ref)[:10])
 
 
 @pytest.mark.parametrize("h", [1, 2, 3, 5])
@@ -76,7 +80,7 @@ def test_running_example(ctx):
 @pytest.mark.parametrize("h", [1, 2, 3, 4])
 def test_chung_lu_2000(ctx, h):
     g = synth.chung_lu(2000, 10.0, 2.5, seed=1)
-    _check(ctx, g, h, widths=(1, 16))
+    _check(ctx, g, h, widths=(8, 32))
 
 
 @pytest.mark.parametrize("h", [2, 3, 4])
