@@ -84,8 +84,9 @@ const char *khc_last_error(const khc_ctx *ctx);
 #define KHC_OPT_VALIDATE 4        /* 1 = validate the CSR in khc_graph_create (default 1)               */
 #define KHC_OPT_WAVES_PER_CU 5    /* wavefronts per CU for the BFS level kernels (4..32; default 16)     */
 #define KHC_OPT_PROFILE 6         /* 1 = time every BFS kernel launch with HIP events (default 0)       */
-#define KHC_OPT_DRIVER 7          /* decomposition driver: 0 = host loop over rounds, 1 = one persistent
-                                     kernel captured in a hipGraph (default 1)                        */
+#define KHC_OPT_DRIVER 7          /* single-graph decomposition driver: 0 = host loop over rounds
+                                     (default), 1 = one persistent kernel captured in a hipGraph;
+                                     batched graphs always use the persistent kernel                  */
 #define KHC_OPT_PERSIST_WIDTH 8   /* uint64 words per vertex per BFS batch in the persistent driver
                                      (8, 16 or 32; default 32)                                        */
 #define KHC_OPT_BARRIER_TIMEOUT 9 /* seconds a grid-barrier wait may take before the persistent kernel

@@ -263,6 +263,10 @@ int khc_create(khc_ctx **out, int device, void *hip_stream) {
     c->bufs.resize(WS_NUM_SLOTS);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
+    if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        c->capture_stream = nullptr;
+    }
     int rate_khz = 0;
     if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate_khz > 0)
         c->wall_clock_khz = (uint64_t)rate_khz;
@@ -280,6 +284,7 @@ int khc_destroy(khc_ctx *ctx) {
     (void)hipSetDevice(ctx->device);
     (void)hipStreamSynchronize(ctx->stream);
     drop_persist_graphs(ctx, nullptr);
+    if (ctx->capture_stream) (void)hipStreamDestroy(ctx->capture_stream);
     for (auto &b : ctx->bufs)
         if (b.ptr) (void)hipFree(b.ptr);
     for (auto &r : ctx->prof_pending) {

@@ -67,7 +67,7 @@ struct khc_ctx {
     std::vector<hipEvent_t> prof_pool;
     khc_profile prof_acc{};
     // persistent driver
-    int driver = 1;             // 0 host-driven rounds, 1 one persistent kernel
+    int driver = 0;             // 0 host-driven rounds, 1 one persistent kernel
     int persist_width = 32;     // source words per BFS batch in the persistent kernel
     int barrier_timeout_s = 20; // deadline of one grid-barrier wait
     uint64_t wall_clock_khz = 100000;
@@ -83,6 +83,7 @@ struct khc_ctx {
         }
     };
     std::vector<PersistGraph> persist_graphs;
+    hipStream_t capture_stream = nullptr;  // private stream the persistent launch is captured on
 };
 
 struct khc_graph {

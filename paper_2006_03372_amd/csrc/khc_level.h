@@ -344,8 +344,11 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                                   : p.n_chunks + (p.n_light + GROUPS * PASSES - 1) / (GROUPS * PASSES);
     __syncthreads();
 
-    for (;;) {
-        if (tid == 0) s_item = atomicAdd(p.work, 1u);
+    // The first item of each workgroup is its block index; later items come
+    // from the counter (offset by the grid size), so workgroups without
+    // work leave without touching it.
+    for (bool first = true;; first = false) {
+        if (tid == 0) s_item = first ? blockIdx.x : gridDim.x + atomicAdd(p.work, 1u);
         __syncthreads();
         const uint32_t item = s_item;
         if (item >= n_items) break;

@@ -48,11 +48,25 @@ struct PCtl {
     unsigned long long stat_hrec, stat_hm1, stat_aff, stat_batches;
 };
 
+// Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
+// XCD b % 8; checked on the device), and each XCD has its own L2, which is
+// not coherent with the others for ordinary device memory.  The barrier
+// therefore groups workgroups by XCD: members release at workgroup scope
+// (their stores reach the XCD's L2) and, after the barrier, invalidate only
+// their CU's L1; the last arrival of each XCD writes back and invalidates
+// that XCD's L2 once (agent-scope fences) around the global step.
+constexpr uint32_t kXcds = 8;
+
+// Barrier words: count[0] global arrivals, gen[0] global generation,
+// abort[0]; then per group g: gcount[g], ggen[g] (each on its own 128-byte
+// line to keep pollers of different groups apart).
 struct Sync {
     uint32_t *count;
     uint32_t *gen;
     uint32_t *abort;
+    uint32_t *groups;  // group g: groups[g * 32] arrivals, groups[g * 32 + 16] generation
     uint32_t nblocks;
+    uint32_t ngroups;
     uint64_t timeout_ticks;
 };
 
@@ -90,36 +104,53 @@ struct PParams {
     Sync sync;
 };
 
-// Grid barrier.  Thread 0 of each workgroup arrives with an atomic; the
-// last arrival resets the count and bumps the generation.  Waiters poll the
-// generation with a deadline and the abort flag.  Returns false if the
-// kernel must exit.
+// Wait until *word != g; false on abort or deadline (which raises abort).
+__device__ bool wait_change(const Sync &s, const uint32_t *word, uint32_t g) {
+    const uint64_t t0 = wall_clock64();
+    while (__hip_atomic_load(word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
+        if (__hip_atomic_load(s.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
+        if (wall_clock64() - t0 > s.timeout_ticks) {
+            atomicExch(s.abort, 1u);
+            return false;
+        }
+        __builtin_amdgcn_s_sleep(1);
+    }
+    return true;
+}
+
+// Two-level grid barrier.  Thread 0 of each workgroup arrives at its
+// group's counter; the last of a group arrives at the global counter; the
+// last group resets the global counter and bumps the global generation.
+// Each group's last arrival waits for the global generation and then bumps
+// its group's generation, which the rest of the group polls.  Every wait
+// has a deadline and watches the abort flag.  Returns false if the kernel
+// must exit.
 __device__ bool grid_sync(const Sync &s, uint32_t *s_gen, uint32_t *s_ok) {
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t g = *s_gen;
+        const uint32_t grp = blockIdx.x % kXcds;
+        const uint32_t gsize = s.nblocks / kXcds + (grp < s.nblocks % kXcds ? 1u : 0u);
+        uint32_t *gcount = s.groups + grp * 32;
+        uint32_t *ggen = s.groups + grp * 32 + 16;
         uint32_t ok = 1;
-        __threadfence();
-        if (atomicAdd(s.count, 1u) == s.nblocks - 1) {
-            atomicExch(s.count, 0u);
-            __threadfence();
-            atomicAdd(s.gen, 1u);
-        } else {
-            const uint64_t t0 = wall_clock64();
-            while (__hip_atomic_load(s.gen, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
-                if (__hip_atomic_load(s.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) {
-                    ok = 0;
-                    break;
-                }
-                if (wall_clock64() - t0 > s.timeout_ticks) {
-                    atomicExch(s.abort, 1u);
-                    ok = 0;
-                    break;
-                }
-                __builtin_amdgcn_s_sleep(1);
+        __atomic_thread_fence(__ATOMIC_RELEASE);  // workgroup scope: stores reach this XCD's L2
+        if (atomicAdd(gcount, 1u) == gsize - 1) {
+            atomicExch(gcount, 0u);
+            __threadfence();  // write back this XCD's L2
+            if (atomicAdd(s.count, 1u) == s.ngroups - 1) {
+                atomicExch(s.count, 0u);
+                __threadfence();
+                atomicAdd(s.gen, 1u);
+            } else {
+                ok = wait_change(s, s.gen, g) ? 1u : 0u;
             }
+            __threadfence();  // invalidate this XCD's L2 (and this CU's L1)
+            atomicAdd(ggen, 1u);
+        } else {
+            ok = wait_change(s, ggen, g) ? 1u : 0u;
+            asm volatile("buffer_inv sc0" ::: "memory");  // invalidate this CU's L1
         }
-        __threadfence();
         if (__hip_atomic_load(s.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
         *s_gen = g + 1;
         *s_ok = ok;
@@ -586,10 +617,8 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
     }
 }
 
-__global__ void sync_reset_kernel(uint32_t *count, uint32_t *gen, uint32_t *abort) {
-    *count = 0;
-    *gen = 0;
-    *abort = 0;
+__global__ void sync_reset_kernel(uint32_t *words, uint32_t nwords) {
+    for (uint32_t i = threadIdx.x; i < nwords; i += blockDim.x) words[i] = 0;
 }
 
 template <int W>
@@ -651,7 +680,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
         (rc = ws_get(ctx, WS_GRAPHK, (size_t)g->ngraphs * 8 + 8, &kg)) ||
         (rc = ws_get(ctx, WS_AHQ, (size_t)(h + 1) * ahq_len * 8, &ahq)) ||
         (rc = ws_get(ctx, WS_CTL, sizeof(PCtl), &ctl)) ||
-        (rc = ws_get(ctx, WS_SYNC, 64, &sync)))
+        (rc = ws_get(ctx, WS_SYNC, (size_t)(32 + 32 * kXcds) * 4, &sync)))
         return rc;
     ming = (uint32_t *)kg + g->ngraphs;
     PParams p;
@@ -703,8 +732,9 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.bhcnt = p.bqcnt + nq;
     uint32_t *sp = (uint32_t *)sync;
     p.sync.count = sp;
-    p.sync.gen = sp + 1;
-    p.sync.abort = sp + 2;
+    p.sync.gen = sp + 16;
+    p.sync.abort = sp + 8;
+    p.sync.groups = sp + 32;
     int grid = -1;
     switch (W) {
         case 8: grid = persistent_grid<8>(ctx); break;
@@ -713,6 +743,8 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     }
     if (grid < 1) return set_error(ctx, KHC_EHIP, "occupancy query for the persistent kernel failed");
     p.sync.nblocks = (uint32_t)grid;
+    p.sync.ngroups = (uint32_t)grid < kXcds ? (uint32_t)grid : kXcds;
+    const uint32_t sync_words = 32 + 32 * p.sync.ngroups;
     p.sync.timeout_ticks = (uint64_t)ctx->wall_clock_khz * 1000ull * (uint64_t)ctx->barrier_timeout_s;
     hipStream_t st = ctx->stream;
 
@@ -722,16 +754,19 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     for (auto &e : ctx->persist_graphs)
         if (e.same_args(key)) exec = e.exec;
     if (!exec) {
+        // captured on the context's private stream, launched on its work stream
+        hipStream_t cs = ctx->capture_stream;
+        if (!cs) return set_error(ctx, KHC_EHIP, "no capture stream");
         hipGraph_t graph;
-        hipError_t e = hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal);
+        hipError_t e = hipStreamBeginCapture(cs, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return check_hip(ctx, e, "graph capture begin");
-        hipLaunchKernelGGL(sync_reset_kernel, dim3(1), dim3(1), 0, st, p.sync.count, p.sync.gen, p.sync.abort);
+        hipLaunchKernelGGL(sync_reset_kernel, dim3(1), dim3(256), 0, cs, sp, sync_words);
         switch (W) {
-            case 8: launch_persistent<8>(p, grid, st); break;
-            case 16: launch_persistent<16>(p, grid, st); break;
-            default: launch_persistent<32>(p, grid, st); break;
+            case 8: launch_persistent<8>(p, grid, cs); break;
+            case 16: launch_persistent<16>(p, grid, cs); break;
+            default: launch_persistent<32>(p, grid, cs); break;
         }
-        e = hipStreamEndCapture(st, &graph);
+        e = hipStreamEndCapture(cs, &graph);
         if (e != hipSuccess) return check_hip(ctx, e, "graph capture end");
         e = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
@@ -744,10 +779,10 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     PCtl host_ctl;
     uint32_t host_sync[3];
     e = hipMemcpyAsync(&host_ctl, ctl, sizeof(PCtl), hipMemcpyDeviceToHost, st);
-    if (e == hipSuccess) e = hipMemcpyAsync(host_sync, sync, 12, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipMemcpyAsync(host_sync, sp + 8, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "persistent decomposition");
-    if (host_sync[2]) {
+    if (host_sync[0]) {
         if (host_ctl.abort_reason == 1) return set_error(ctx, KHC_ELIMIT, "a round removed no vertex");
         return set_error(ctx, KHC_EHIP, "persistent decomposition aborted: a grid barrier wait exceeded " +
                                             std::to_string(ctx->barrier_timeout_s) + " s");

@@ -8,6 +8,7 @@ from __future__ import annotations
 
 import ctypes
 import os
+import weakref
 
 import numpy as np
 
@@ -133,6 +134,8 @@ class Context:
         if rc:
             raise KhcError(rc, "khc_create failed")
         self.handle = h
+        # graph handles refer to the context: they are released first
+        self._graphs = weakref.WeakSet()
 
     def _check(self, rc):
         if rc:
@@ -150,6 +153,8 @@ class Context:
 
     def close(self):
         if getattr(self, "handle", None):
+            for g in list(getattr(self, "_graphs", ())):
+                g.close()
             self.lib.khc_destroy(self.handle)
             self.handle = None
 
@@ -235,10 +240,12 @@ class Graph:
         h = ctypes.c_void_p()
         ctx._check(ctx.lib.khc_graph_create(ctx.handle, ctypes.byref(s), ctypes.byref(h)))
         self.handle = h
+        ctx._graphs.add(self)
 
     def close(self):
         if getattr(self, "handle", None):
-            self.ctx.lib.khc_graph_destroy(self.handle)
+            if getattr(self.ctx, "handle", None):
+                self.ctx.lib.khc_graph_destroy(self.handle)
             self.handle = None
 
     def __del__(self):
@@ -278,4 +285,5 @@ class BatchedGraph(Graph):
                                                     ctypes.byref(h)))
         del col_dev
         self.handle = h
+        ctx._graphs.add(self)
 
