@@ -190,6 +190,56 @@ int khcore_decompose_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base,
                              const uint32_t *col, uint64_t nnz, uint32_t h, uint32_t *core,
                              uint32_t *peel_round, khc_stats *stats);
 
+/* ---- learned approximate mode ----------------------------------------- */
+
+/* A small MLP that estimates log-scaled h-degrees from eight cheap features
+ * (the paper estimates updated h-degrees by sampling instead, Section
+ * IV-C): 8 inputs -> 64 -> 64 (ReLU) -> 1, BF16 weights and activations in
+ * MFMA with FP32 accumulation, FP32 biases and FP32 master weights trained
+ * with Adam.  Parameter vector (4801 floats, this order): W1[64][8], b1[64],
+ * W2[64][64], b2[64], W3[64], b3; layer l computes W_l x + b_l. */
+typedef struct khc_mlp khc_mlp;
+
+/* He-uniform weights from `seed`, zero biases. */
+int khc_mlp_create(khc_ctx *ctx, uint64_t seed, khc_mlp **out);
+int khc_mlp_destroy(khc_mlp *m);
+/* Host float[4801] in/out (also resets the Adam state on set). */
+int khc_mlp_set_params(khc_ctx *ctx, khc_mlp *m, const float *host_params);
+int khc_mlp_get_params(khc_ctx *ctx, const khc_mlp *m, float *host_params, float *host_grad);
+/* y[i] = network(X[i][0..8)), X device float[n][8], y device float[n].
+ * Asynchronous. */
+int khc_mlp_forward(khc_ctx *ctx, const khc_mlp *m, const float *X, uint32_t n, float *y);
+/* Gradient of sum_i (y_i - target_i)^2 / n over all n rows into the
+ * network's gradient (read it with khc_mlp_get_params); *host_loss gets the
+ * mean squared error.  Synchronous. */
+int khc_mlp_gradient(khc_ctx *ctx, khc_mlp *m, const float *X, const float *target, uint32_t n,
+                     float *host_loss);
+/* Adam training on (X, target) device arrays: `epochs` passes in a seeded
+ * random order, minibatches of `batch` rows, learning rate lr.
+ * host_epoch_loss (host float[epochs] or NULL) gets each epoch's mean
+ * minibatch loss.  Synchronous. */
+int khc_mlp_train(khc_ctx *ctx, khc_mlp *m, const float *X, const float *target, uint32_t n, uint32_t epochs,
+                  uint32_t batch, float lr, uint64_t seed, float *host_epoch_loss);
+
+/* Features of every vertex of G(alive) for the network: X device
+ * float[n][8], each log1p(count) / 8 of exact counts with a = max(1, h-3),
+ * b = max(1, h-2): d^a(v), d^b(v), d^{h-1}(v); min, mean, max over live
+ * neighbours of d^{h-1}; mean over live neighbours of d^a and of d^b.
+ * lb, ub (device uint32[n] or NULL): exact bounds on d^h(v) from d^{h-1}:
+ * max(d^{h-1}(v), max_w d^{h-1}(w)) and min(live - 1, sum_w d^{h-1}(w)).
+ * Dead vertices get zeros.  2 <= h <= 64.  Asynchronous. */
+int khc_features(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h, float *X,
+                 uint32_t *lb, uint32_t *ub);
+
+/* Approximate (k,h)-core numbers: the level-synchronous peeling of
+ * khcore_decompose, with each affected vertex's h-degree replaced by the
+ * network's estimate clamped to [lb, ub] and never raised; exact
+ * (h-1)-hop degrees and features are maintained.  mlp == NULL uses lb as
+ * the estimate.  estimate (device uint32[n] or NULL) gets each vertex's
+ * estimate when it was removed.  2 <= h <= 64.  Synchronous. */
+int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const khc_mlp *mlp,
+                            uint32_t *core, uint32_t *estimate, khc_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

@@ -601,6 +601,36 @@ int khc_graph_destroy(khc_graph *g) {
     return KHC_OK;
 }
 
+}  // extern "C"
+
+namespace khc {
+int compact_sources(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t **srcs_out,
+                    uint32_t *count) {
+    hipStream_t st = ctx->stream;
+    const uint32_t n = g->n;
+    int rc;
+    void *srcs, *cnt;
+    if ((rc = ws_get(ctx, WS_SRCS, (size_t)n * 4 + 4, &srcs)) || (rc = ws_get(ctx, WS_FLAGS, 64, &cnt)))
+        return rc;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)cnt, 0u, (uint64_t)1);
+    hipLaunchKernelGGL(compact_sources_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr, g->col,
+                       alive, (uint32_t *)srcs, (uint32_t *)cnt);
+    hipError_t e = hipMemcpyAsync(ctx->host_scalars, cnt, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(ctx, e, "source compaction");
+    *srcs_out = (uint32_t *)srcs;
+    *count = ctx->host_scalars[0];
+    return KHC_OK;
+}
+
+void fill_u32(khc_ctx *ctx, uint32_t *p, uint32_t value, uint64_t count) {
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(count, 256, 4096)), dim3(256), 0, ctx->stream, p, value,
+                       count);
+}
+}  // namespace khc
+
+extern "C" {
+
 int khdeg_compute(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                   uint32_t *deg) {
     if (!ctx) return KHC_EINVAL;

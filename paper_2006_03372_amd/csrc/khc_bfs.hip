@@ -171,7 +171,7 @@ int width_for(uint32_t cnt, int max_width) {
 // rows instead), scatter the per-lane results, clear the touched rows.
 int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
               const uint32_t *srcs, uint32_t nsrc, uint32_t *deg_list, int scatter,
-              uint32_t *deg_full, uint64_t *te_full) {
+              uint32_t *deg_full, uint64_t *te_full, uint32_t *const *level_out = nullptr) {
     if (nsrc == 0) return KHC_OK;
     const uint32_t levels = te_full ? h - 1 : h;
     const uint32_t n = g->n;
@@ -275,6 +275,10 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
             const int prec = prof_begin(ctx, last ? 3 : (lev == 1 ? 1 : 2), bytes);
             dispatch_level(W, p, grid, last, st);
             prof_end(ctx, prec);
+            // cumulative counts after level lev are the lev-hop degrees
+            if (level_out && level_out[lev - 1] && !last)
+                hipLaunchKernelGGL(batch_scatter_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, srcs, first,
+                                   cnt, (const uint32_t *)counts, (uint32_t *)nullptr, level_out[lev - 1]);
         }
         if (te_full) {
             unsigned long long *tep = (unsigned long long *)te;
@@ -325,6 +329,11 @@ int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
 int msbfs_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                        const uint32_t *srcs, uint32_t nsrc, uint64_t *te_full) {
     return msbfs_run(ctx, g, alive, h, srcs, nsrc, nullptr, 1, nullptr, te_full);
+}
+
+int msbfs_all_levels(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t levels,
+                     const uint32_t *srcs, uint32_t nsrc, uint32_t *const *level_out) {
+    return msbfs_run(ctx, g, alive, levels, srcs, nsrc, nullptr, 1, level_out[levels - 1], nullptr, level_out);
 }
 
 }  // namespace khc

@@ -148,6 +148,10 @@ enum WsSlot {
     WS_AHQ,
     WS_CTL,
     WS_SYNC,
+    WS_APPROX_DJ,
+    WS_APPROX_SCAL,
+    WS_APPROX_X,
+    WS_APPROX_Y,
     WS_NUM_SLOTS
 };
 
@@ -162,6 +166,16 @@ int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
 // over the vertices within h-1 hops of s, s included).  Asynchronous.
 int msbfs_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                        const uint32_t *srcs, uint32_t nsrc, uint64_t *te_full);
+
+// j-hop degrees of the sources for every j = 1..levels: level_out[j-1]
+// (full-length device arrays, indexed by vertex).  Asynchronous.
+int msbfs_all_levels(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t levels,
+                     const uint32_t *srcs, uint32_t nsrc, uint32_t *const *level_out);
+// Live sources (live vertices with a live neighbour) into the WS_SRCS
+// workspace; returns their number in *count (synchronous).
+int compact_sources(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t **srcs,
+                    uint32_t *count);
+void fill_u32(khc_ctx *ctx, uint32_t *p, uint32_t value, uint64_t count);
 
 // Whole decomposition in one persistent kernel (khc_persist.hip).
 int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,

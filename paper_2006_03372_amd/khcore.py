@@ -37,7 +37,11 @@ EXPORTED = [
     "khc_graph_create", "khc_graph_destroy", "khc_validate_csr",
     "khdeg_compute", "khdeg_compute_list", "khdeg_scanned_arcs", "khcore_decompose",
     "khc_graph_create_batched", "khcore_decompose_batched",
+    "khc_mlp_create", "khc_mlp_destroy", "khc_mlp_set_params", "khc_mlp_get_params",
+    "khc_mlp_forward", "khc_mlp_gradient", "khc_mlp_train", "khc_features", "khcore_decompose_approx",
 ]
+
+N_PARAMS = 4801
 
 
 class KhcError(RuntimeError):
@@ -101,6 +105,15 @@ def load_library(path: str = LIB_PATH):
         "khcore_decompose": ([P, P, u32, P, P, ctypes.POINTER(Stats)], i32),
         "khc_graph_create_batched": ([P, u32, P, P, P, u64, PP], i32),
         "khcore_decompose_batched": ([P, u32, P, P, P, u64, u32, P, P, ctypes.POINTER(Stats)], i32),
+        "khc_mlp_create": ([P, u64, PP], i32),
+        "khc_mlp_destroy": ([P], i32),
+        "khc_mlp_set_params": ([P, P, P], i32),
+        "khc_mlp_get_params": ([P, P, P, P], i32),
+        "khc_mlp_forward": ([P, P, P, u32, P], i32),
+        "khc_mlp_gradient": ([P, P, P, P, u32, P], i32),
+        "khc_mlp_train": ([P, P, P, P, u32, u32, u32, ctypes.c_float, u64, P], i32),
+        "khc_features": ([P, P, P, u32, P, P, P], i32),
+        "khcore_decompose_approx": ([P, P, u32, P, P, P, ctypes.POINTER(Stats)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -178,6 +191,29 @@ class Context:
     def batch(self, graphs) -> "BatchedGraph":
         """Pack several host CSRs (synth.CSR) into one batched graph handle."""
         return BatchedGraph(self, graphs)
+
+    def mlp(self, seed: int = 0) -> "Mlp":
+        return Mlp(self, seed)
+
+    def features(self, graph: "Graph", h: int, alive=None):
+        """(X float32 [n, 8], lb, ub) for G(alive) (device tensors)."""
+        torch = _torch()
+        X = torch.empty((graph.n, 8), dtype=torch.float32, device=graph.device)
+        lb = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+        ub = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+        self._check(self.lib.khc_features(self.handle, graph.handle, _dptr(alive), h, _dptr(X),
+                                          _dptr(lb), _dptr(ub)))
+        return X, lb, ub
+
+    def core_approx(self, graph: "Graph", h: int, mlp=None, with_estimate: bool = False):
+        torch = _torch()
+        core = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+        est = torch.empty(graph.n, dtype=torch.int32, device=graph.device) if with_estimate else None
+        st = Stats()
+        self._check(self.lib.khcore_decompose_approx(self.handle, graph.handle, h,
+                                                     None if mlp is None else mlp.handle, _dptr(core),
+                                                     _dptr(est), ctypes.byref(st)))
+        return core, est, st.as_dict()
 
     def validate(self, row_ptr, col, n: int) -> int:
         """Validate a device CSR; returns the status code (0 = ok)."""
@@ -286,4 +322,60 @@ class BatchedGraph(Graph):
         del col_dev
         self.handle = h
         ctx._graphs.add(self)
+
+
+class Mlp:
+    """The learned-mode network (device parameters, Adam state)."""
+
+    def __init__(self, ctx: Context, seed: int = 0):
+        self.ctx = ctx
+        h = ctypes.c_void_p()
+        ctx._check(ctx.lib.khc_mlp_create(ctx.handle, seed, ctypes.byref(h)))
+        self.handle = h
+
+    def close(self):
+        if getattr(self, "handle", None):
+            if getattr(self.ctx, "handle", None):
+                self.ctx.lib.khc_mlp_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def get(self):
+        p = np.zeros(N_PARAMS, dtype=np.float32)
+        g = np.zeros(N_PARAMS, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.khc_mlp_get_params(self.ctx.handle, self.handle,
+                                                         p.ctypes.data_as(ctypes.c_void_p),
+                                                         g.ctypes.data_as(ctypes.c_void_p)))
+        return p, g
+
+    def set(self, params):
+        p = np.ascontiguousarray(params, dtype=np.float32)
+        assert p.size == N_PARAMS
+        self.ctx._check(self.ctx.lib.khc_mlp_set_params(self.ctx.handle, self.handle,
+                                                         p.ctypes.data_as(ctypes.c_void_p)))
+
+    def forward(self, X):
+        torch = _torch()
+        y = torch.empty(X.shape[0], dtype=torch.float32, device=X.device)
+        self.ctx._check(self.ctx.lib.khc_mlp_forward(self.ctx.handle, self.handle, _dptr(X), X.shape[0],
+                                                      _dptr(y)))
+        return y
+
+    def gradient(self, X, t):
+        loss = ctypes.c_float()
+        self.ctx._check(self.ctx.lib.khc_mlp_gradient(self.ctx.handle, self.handle, _dptr(X), _dptr(t),
+                                                       X.shape[0], ctypes.byref(loss)))
+        return loss.value
+
+    def train(self, X, t, epochs: int, batch: int = 4096, lr: float = 1e-3, seed: int = 0):
+        losses = np.zeros(epochs, dtype=np.float32)
+        self.ctx._check(self.ctx.lib.khc_mlp_train(self.ctx.handle, self.handle, _dptr(X), _dptr(t),
+                                                    X.shape[0], epochs, batch, lr, seed,
+                                                    losses.ctypes.data_as(ctypes.c_void_p)))
+        return losses
 

@@ -1,0 +1,153 @@
+"""GPU learned mode: MLP forward and backward against the reference
+(bf16 contract), training, features against the CPU oracle, and the gain of
+the trained network over the bound-only estimator."""
+import numpy as np
+import pytest
+
+import oracle
+from oracle import mlp as omlp
+from paper_2006_03372_amd import synth
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.fixture(scope="module")
+def ctx():
+    import torch
+    from paper_2006_03372_amd import khcore
+    c = khcore.Context(0)
+    yield c
+    torch.cuda.synchronize()
+    c.close()
+
+
+def _rand_params(seed, scale=0.25):
+    rng = np.random.default_rng(seed)
+    p = rng.normal(0.0, scale, size=omlp.N_PARAMS)
+    return p.astype(np.float32)
+
+
+@pytest.mark.parametrize("n", [16, 1000, 4099])
+def test_forward_matches_reference(ctx, n):
+    import torch
+    net = ctx.mlp(seed=1)
+    p = _rand_params(n)
+    net.set(p)
+    X = np.random.default_rng(n + 1).uniform(0.0, 1.6, size=(n, 8)).astype(np.float32)
+    y = net.forward(torch.from_numpy(X).cuda()).cpu().numpy().astype(np.float64)
+    ref, _ = omlp.forward(p, X, exact=False)
+    err = np.abs(y - ref)
+    print(f"forward n={n}: max err {err.max():.3e} mean {err.mean():.3e}", flush=True)
+    assert err.max() <= 2e-2 * (1.0 + np.abs(ref).max())
+    assert err.mean() <= 2e-3 * (1.0 + np.abs(ref).mean())
+    net.close()
+
+
+def test_backward_matches_reference(ctx):
+    import torch
+    net = ctx.mlp(seed=2)
+    p = _rand_params(7)
+    net.set(p)
+    rng = np.random.default_rng(8)
+    n = 777
+    X = rng.uniform(0.0, 1.6, size=(n, 8)).astype(np.float32)
+    t = rng.uniform(0.0, 1.5, size=n).astype(np.float32)
+    loss = net.gradient(torch.from_numpy(X).cuda(), torch.from_numpy(t).cuda())
+    _, g = net.get()
+    g_ref = omlp.backward(p, X, t, exact=False)
+    l_ref = float(np.mean((omlp.forward(p, X, exact=False)[0] - t) ** 2))
+    rel = np.linalg.norm(g - g_ref) / np.linalg.norm(g_ref)
+    print(f"backward: loss {loss:.6f} vs {l_ref:.6f}, relative gradient error {rel:.3e}", flush=True)
+    assert abs(loss - l_ref) <= 1e-2 * max(l_ref, 1e-6)
+    assert rel < 3e-2
+    # the bf16 contract stays close to the exact float64 gradient, which is
+    # itself pinned to finite differences on the CPU
+    g64 = omlp.backward(p, X, t, exact=True)
+    assert np.linalg.norm(g - g64) / np.linalg.norm(g64) < 8e-2
+    net.close()
+
+
+def test_training_reduces_loss(ctx):
+    import torch
+    teacher = _rand_params(11, 0.3)
+    rng = np.random.default_rng(12)
+    X = rng.uniform(0.0, 1.6, size=(20000, 8)).astype(np.float32)
+    t, _ = omlp.forward(teacher, X, exact=True)
+    net = ctx.mlp(seed=3)
+    losses = net.train(torch.from_numpy(X).cuda(), torch.from_numpy(t.astype(np.float32)).cuda(),
+                       epochs=12, batch=1024, lr=3e-3, seed=5)
+    print("epoch losses", losses, flush=True)
+    assert np.all(np.isfinite(losses))
+    assert losses[-1] < 0.2 * losses[0]
+    net.close()
+
+
+@pytest.mark.parametrize("h", [2, 3, 4])
+def test_features_match_oracle(ctx, h):
+    import torch
+    g = synth.chung_lu(1500, 8.0, 2.5, seed=4)
+    alive = synth.random_alive(g.n, 0.8, 9)
+    gr = ctx.graph(g)
+    X, lb, ub = ctx.features(gr, h, torch.from_numpy(alive).cuda())
+    X = X.cpu().numpy()
+    lb = lb.cpu().numpy().view(np.uint32)
+    ub = ub.cpu().numpy().view(np.uint32)
+    gr.close()
+    a, b = max(1, h - 3), max(1, h - 2)
+    dj = {j: oracle.hdeg(g, j, alive).astype(np.float64) for j in sorted({a, b, h - 1})}
+    live = alive.astype(bool)
+    n_live = int(live.sum())
+    for v in range(g.n):
+        if not live[v]:
+            assert not X[v].any() and lb[v] == 0 and ub[v] == 0
+            continue
+        nb = [w for w in g.col[g.row_ptr[v]:g.row_ptr[v + 1]] if live[w]]
+        c = dj[h - 1][nb] if nb else np.zeros(0)
+        f = [dj[a][v], dj[b][v], dj[h - 1][v]]
+        if nb:
+            f += [c.min(), c.mean(), c.max(), dj[a][nb].mean(), dj[b][nb].mean()]
+        else:
+            f += [0.0] * 5
+        ref = np.log1p(np.array(f)) / 8.0
+        assert np.allclose(X[v], ref, rtol=1e-5, atol=1e-6), (v, X[v], ref)
+        assert lb[v] == int(max(dj[h - 1][v], c.max() if nb else 0))
+        assert ub[v] == max(int(lb[v]), int(min(n_live - 1, c.sum())))
+
+
+def test_bounds_bracket_exact_degree(ctx):
+    import torch
+    g = synth.rmat(11, 8, seed=6)
+    for h in (2, 3, 4):
+        gr = ctx.graph(g)
+        _, lb, ub = ctx.features(gr, h)
+        d = ctx.hdeg(gr, h)
+        gr.close()
+        lb, ub, d = (t.cpu().numpy().view(np.uint32) for t in (lb, ub, d))
+        assert (lb <= d).all() and (d <= ub).all()
+
+
+def test_learned_mode_beats_bounds_only(ctx):
+    """Train on exact h-degrees of peeling states of small R-MAT graphs, then
+    peel an unseen R-MAT graph: the network must give more exact core numbers
+    than the estimator that uses the lower bound alone."""
+    import torch
+    from paper_2006_03372_amd import learned
+    h = 4
+    train_graphs = [synth.rmat(11, 8, seed=101 + i) for i in range(6)]
+    X, t = learned.training_set(ctx, train_graphs, h)
+    net = ctx.mlp(seed=7)
+    losses = net.train(X, t, epochs=25, batch=2048, lr=2e-3, seed=1)
+    print("training samples", X.shape[0], "losses", losses[[0, -1]], flush=True)
+    test = synth.rmat(12, 8, seed=1)
+    gr = ctx.graph(test)
+    exact, _, _ = ctx.core(gr, h)
+    learned_core, _, st = ctx.core_approx(gr, h, net)
+    bound_core, _, _ = ctx.core_approx(gr, h, None)
+    gr.close()
+    e = exact.cpu().numpy().view(np.uint32)
+    acc_l = learned.accuracy(e, learned_core.cpu().numpy().view(np.uint32))
+    acc_b = learned.accuracy(e, bound_core.cpu().numpy().view(np.uint32))
+    print("learned", acc_l, "bounds only", acc_b, "rounds", st["rounds"], flush=True)
+    assert acc_l["exact_fraction"] > acc_b["exact_fraction"]
+    assert acc_l["mae"] < acc_b["mae"]
+    net.close()
