@@ -217,7 +217,9 @@ int khc_mlp_gradient(khc_ctx *ctx, khc_mlp *m, const float *X, const float *targ
 /* Adam training on (X, target) device arrays: `epochs` passes in a seeded
  * random order, minibatches of `batch` rows, learning rate lr.
  * host_epoch_loss (host float[epochs] or NULL) gets each epoch's mean
- * minibatch loss.  Synchronous. */
+ * minibatch loss.  Gradients are summed in a fixed order, so the same
+ * seeds, data and device give the same parameters bit for bit.
+ * Synchronous. */
 int khc_mlp_train(khc_ctx *ctx, khc_mlp *m, const float *X, const float *target, uint32_t n, uint32_t epochs,
                   uint32_t batch, float lr, uint64_t seed, float *host_epoch_loss);
 

@@ -27,7 +27,7 @@
 #include <cstring>
 #include <vector>
 
-#include "khc_internal.h"
+#include "khc_round.h"
 
 namespace khc {
 float *mlp_params(khc_mlp *m);
@@ -37,6 +37,8 @@ extern "C" int khc_mlp_forward(khc_ctx *ctx, const khc_mlp *m, const float *X, u
 
 namespace khc {
 namespace {
+
+using namespace rnd;
 
 constexpr float kFeatScale = 8.f;
 constexpr int kFeat = 8;
@@ -129,86 +131,14 @@ __global__ void live_count_kernel(uint32_t n, const uint8_t *alive, uint32_t *ou
     if ((threadIdx.x & 63) == 0 && c) atomicAdd(out, c);
 }
 
-enum : int { AS_MIN = 0, AS_K = 1, AS_TOT = 2, AS_LIVE = 3, AS_ENDS = 4 };
-
-__global__ void amin_kernel(uint32_t n, const uint8_t *alive, const uint32_t *d, uint32_t *scal) {
-    uint32_t m = 0xFFFFFFFFu;
-    for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x)
-        if (alive[v] && d[v] < m) m = d[v];
-    for (int off = 32; off > 0; off >>= 1) {
-        const uint32_t o = __shfl_down(m, off, 64);
-        m = o < m ? o : m;
-    }
-    if ((threadIdx.x & 63) == 0 && m != 0xFFFFFFFFu) atomicMin(&scal[AS_MIN], m);
-}
-
-__global__ void around_begin_kernel(uint32_t *scal) {
-    const uint32_t m = scal[AS_MIN];
-    if (m != 0xFFFFFFFFu && m > scal[AS_K]) scal[AS_K] = m;
-    scal[AS_MIN] = 0xFFFFFFFFu;
-    scal[AS_TOT] = 0;
-}
-
-__global__ void aselect_kernel(uint32_t n, const uint8_t *alive, const uint32_t *d, uint32_t *mark,
-                               uint32_t *core, uint32_t *queue, uint32_t *scal) {
-    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    const uint32_t k = scal[AS_K];
-    const bool take = v < n && alive[v] && d[v] <= k;
-    const uint64_t m = __ballot(take);
-    if (!m) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __builtin_ctzll(m);
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(&scal[AS_TOT], (uint32_t)__builtin_popcountll(m));
-    base = __shfl(base, leader, 64);
-    if (take) {
-        core[v] = k;
-        mark[v] = 1;
-        queue[base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = v;
-    }
-}
-
-__global__ void asnap_kernel(uint32_t *scal, int slot) { scal[AS_ENDS + slot] = scal[AS_TOT]; }
-
-__global__ void aaffected_kernel(const uint64_t *row_ptr, const uint32_t *col, const uint8_t *alive,
-                                 uint32_t *mark, uint32_t *queue, uint32_t *scal, int level) {
-    const uint32_t begin = level >= 2 ? scal[AS_ENDS + level - 2] : 0u;
-    const uint32_t end = scal[AS_ENDS + level - 1];
-    const int lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t i = begin + wave; i < end; i += nwaves) {
-        const uint32_t x = queue[i];
-        for (uint64_t a = row_ptr[x] + lane; a < row_ptr[x + 1]; a += 64) {
-            const uint32_t y = col[a];
-            if (alive[y] && mark[y] == 0u && atomicCAS(&mark[y], 0u, 1u) == 0u) queue[atomicAdd(&scal[AS_TOT], 1u)] = y;
-        }
-    }
-}
-
-__global__ void akill_kernel(const uint32_t *queue, uint32_t *scal, uint8_t *alive) {
-    const uint32_t np = scal[AS_ENDS];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x)
-        alive[queue[i]] = 0;
-    if (blockIdx.x == 0 && threadIdx.x == 0) scal[AS_LIVE] -= np;
-}
-
-__global__ void aunmark_kernel(const uint32_t *queue, const uint32_t *scal, uint32_t *mark) {
-    const uint32_t tot = scal[AS_TOT];
-    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gridDim.x * blockDim.x)
-        mark[queue[i]] = 0;
-}
-
-__global__ void ainit_kernel(uint32_t n, uint8_t *alive, uint32_t *mark, uint32_t *core, uint32_t *scal,
-                             int nscal) {
+__global__ void ainit_kernel(uint32_t n, uint8_t *alive, uint32_t *mark, uint32_t *core, uint32_t *s, int nscal) {
     for (uint32_t v = blockIdx.x * blockDim.x + threadIdx.x; v < n; v += gridDim.x * blockDim.x) {
         alive[v] = 1;
         mark[v] = 0;
         core[v] = 0;
     }
     if (blockIdx.x == 0)
-        for (int i = threadIdx.x; i < nscal; i += blockDim.x)
-            scal[i] = i == AS_MIN ? 0xFFFFFFFFu : (i == AS_LIVE ? n : 0u);
+        for (int i = threadIdx.x; i < nscal; i += blockDim.x) s[i] = i == R_LIVE ? n : 0u;
 }
 
 int grid_of(khc_ctx *ctx, uint64_t count, int threads) {
@@ -281,20 +211,23 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
         return KHC_OK;
     }
     hipStream_t st = ctx->stream;
-    const int nscal = AS_ENDS + (int)h + 2;
+    const int nscal = R_CNT + (int)h + 2;
     int rc;
-    void *alive_v, *mark_v, *queue_v, *scal_v, *dhat_v, *lb_v, *ub_v, *x_v, *y_v, *dj_v;
+    void *alive_v, *mark_v, *queue_v, *scal_v, *dhat_v, *lb_v, *ub_v, *x_v, *y_v, *dj_v, *part_v;
     if ((rc = ws_get(ctx, WS_ALIVE, (size_t)n + 8, &alive_v)) || (rc = ws_get(ctx, WS_MARK, (size_t)n * 4 + 8, &mark_v)) ||
         (rc = ws_get(ctx, WS_QUEUE0, (size_t)n * 4 + 8, &queue_v)) ||
-        (rc = ws_get(ctx, WS_SCRATCH, (size_t)nscal * 4, &scal_v)) ||
+        (rc = ws_get(ctx, WS_SCRATCH, (size_t)nscal * 4 + (size_t)(h + 2) * 8 + 64, &scal_v)) ||
         (rc = ws_get(ctx, WS_DEG, (size_t)n * 4 + 8, &dhat_v)) || (rc = ws_get(ctx, WS_LB, (size_t)n * 4 + 8, &lb_v)) ||
         (rc = ws_get(ctx, WS_DHM1, (size_t)n * 4 + 8, &ub_v)) ||
         (rc = ws_get(ctx, WS_APPROX_X, (size_t)n * kFeat * 4 + 32, &x_v)) ||
         (rc = ws_get(ctx, WS_APPROX_Y, (size_t)n * 4 + 8, &y_v)) ||
-        (rc = ws_get(ctx, WS_APPROX_DJ, (size_t)(h - 1) * n * 4 + 4, &dj_v)))
+        (rc = ws_get(ctx, WS_APPROX_DJ, (size_t)(h - 1) * n * 4 + 4, &dj_v)) ||
+        (rc = ws_get(ctx, WS_MINPART, (size_t)kMinBlocks * 4, &part_v)))
         return rc;
     uint8_t *alive = (uint8_t *)alive_v;
     uint32_t *mark = (uint32_t *)mark_v, *queue = (uint32_t *)queue_v, *scal = (uint32_t *)scal_v;
+    unsigned long long *s64 = (unsigned long long *)((char *)scal_v + (((size_t)nscal * 4 + 63) / 64) * 64);
+    uint32_t *part = (uint32_t *)part_v;
     uint32_t *dhat = estimate ? estimate : (uint32_t *)dhat_v;
     uint32_t *lb = (uint32_t *)lb_v, *ub = (uint32_t *)ub_v;
     float *X = (float *)x_v, *Y = (float *)y_v;
@@ -312,7 +245,7 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
     sl.hm1_recomputes += n;
     // initial estimates of every vertex
     hipLaunchKernelGGL(features_kernel, dim3(wgrid), dim3(256), 0, st, (const uint32_t *)nullptr, n, g->row_ptr,
-                       g->col, alive, dj[a - 1], dj[b - 1], dj[h - 2], (const uint32_t *)(scal + AS_LIVE), X, lb, ub);
+                       g->col, alive, dj[a - 1], dj[b - 1], dj[h - 2], (const uint32_t *)(scal + R_LIVE), X, lb, ub);
     if (mlp && (rc = khc_mlp_forward(ctx, mlp, X, n, Y))) return rc;
     hipLaunchKernelGGL(estimate_kernel, dim3(gn), dim3(256), 0, st, (const uint32_t *)nullptr, n,
                        mlp ? (const float *)Y : (const float *)nullptr, lb, ub, dhat, 0);
@@ -322,21 +255,23 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
     uint32_t *hs = ctx->host_scalars;
     while (left > 0) {
         if ((uint64_t)r > (uint64_t)n) return set_error(ctx, KHC_ELIMIT, "more rounds than vertices");
-        hipLaunchKernelGGL(amin_kernel, dim3(gn), dim3(256), 0, st, n, alive, dhat, scal);
-        hipLaunchKernelGGL(around_begin_kernel, dim3(1), dim3(1), 0, st, scal);
-        hipLaunchKernelGGL(aselect_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, alive, dhat, mark, core,
-                           queue, scal);
-        hipLaunchKernelGGL(asnap_kernel, dim3(1), dim3(1), 0, st, scal, 0);
-        for (uint32_t lev = 1; lev <= h; ++lev) {
-            hipLaunchKernelGGL(aaffected_kernel, dim3(wgrid), dim3(256), 0, st, g->row_ptr, g->col, alive, mark,
-                               queue, scal, (int)lev);
-            hipLaunchKernelGGL(asnap_kernel, dim3(1), dim3(1), 0, st, scal, (int)lev);
-        }
-        hipLaunchKernelGGL(akill_kernel, dim3(gn), dim3(256), 0, st, queue, scal, alive);
+        hipLaunchKernelGGL(keymin_kernel, dim3(kMinBlocks), dim3(256), 0, st, n, alive, (const uint8_t *)nullptr,
+                           dhat, (const uint32_t *)nullptr, part, scal, s64, (int)h);
+        hipLaunchKernelGGL(select_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr, alive,
+                           (const uint8_t *)nullptr, dhat, part, mark, core, (uint32_t *)nullptr, r, queue, scal, s64);
+        for (uint32_t lev = 1; lev <= h; ++lev)
+            hipLaunchKernelGGL(affected_kernel, dim3(wgrid), dim3(256), 0, st, n, g->nnz, g->row_ptr, g->col, alive,
+                               mark, queue, scal, s64, (int)lev);
+        hipLaunchKernelGGL(kill_kernel, dim3(gn), dim3(256), 0, st, queue, scal, alive);
         hipError_t e = hipMemcpyAsync(hs, scal, (size_t)nscal * 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return check_hip(ctx, e, "approx round readback");
-        const uint32_t np = hs[AS_ENDS], tot = hs[AS_TOT], nm = hs[AS_ENDS + h - 1];
+        const uint32_t np = hs[R_CNT];
+        uint32_t nm = 0, tot = 0;
+        for (uint32_t j = 0; j <= h; ++j) {
+            if (j < h) nm += hs[R_CNT + j];
+            tot += hs[R_CNT + j];
+        }
         if (np == 0) return set_error(ctx, KHC_ELIMIT, "round removed no vertex");
         // exact j-hop degrees change only within h-1 hops of P
         if (nm > np) {
@@ -348,13 +283,14 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
         if (na) {
             hipLaunchKernelGGL(features_kernel, dim3(wgrid), dim3(256), 0, st, (const uint32_t *)(queue + np), na,
                                g->row_ptr, g->col, alive, dj[a - 1], dj[b - 1], dj[h - 2],
-                               (const uint32_t *)(scal + AS_LIVE), X, lb, ub);
+                               (const uint32_t *)(scal + R_LIVE), X, lb, ub);
             if (mlp && (rc = khc_mlp_forward(ctx, mlp, X, na, Y))) return rc;
             hipLaunchKernelGGL(estimate_kernel, dim3(grid_of(ctx, na, 256)), dim3(256), 0, st,
                                (const uint32_t *)(queue + np), na, mlp ? (const float *)Y : (const float *)nullptr,
                                lb, ub, dhat, 1);
         }
-        hipLaunchKernelGGL(aunmark_kernel, dim3(gn), dim3(256), 0, st, queue, scal, mark);
+        hipLaunchKernelGGL(finish_kernel, dim3(gn), dim3(256), 0, st, queue, scal, (int)h, mark, (uint8_t *)nullptr,
+                           (uint8_t)0);
         sl.affected_total += na;
         left -= np;
         ++r;
@@ -362,7 +298,7 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "approx end");
     sl.rounds = r;
-    sl.max_level = hs[AS_K];
+    sl.max_level = hs[R_K];
     sl.wall_ms = std::chrono::duration<double, std::milli>(std::chrono::steady_clock::now() - t0).count();
     if (stats) *stats = sl;
     return KHC_OK;

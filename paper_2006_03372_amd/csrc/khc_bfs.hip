@@ -51,17 +51,63 @@ __global__ void batch_seed_kernel(const uint32_t *srcs, uint32_t first, uint32_t
     add_push_items(f, s, ds);
 }
 
-// Zero the W words of every row on a frontier list in `buf` (and, if given,
-// the row's word of a frontier map).
-__global__ void clear_rows_kernel(const uint32_t *q, const uint32_t *qcnt, uint64_t *buf, int W,
-                                  uint32_t *fnz) {
-    const uint32_t cnt = *qcnt;
-    const size_t stride = (size_t)gridDim.x * blockDim.x;
-    for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < (size_t)cnt * W; i += stride)
-        buf[(size_t)q[i / W] * W + (i % W)] = 0;
-    if (fnz)
-        for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < cnt; i += stride)
-            fnz[q[i] >> 5] = 0;
+// End of a batch, in one launch: per-lane results to their sources, the
+// touched rows cleared (vis rows of every frontier list, frontier buffer
+// rows and map words of the last two lists; older ones were cleared by the
+// levels), and the other counter set zeroed for the next batch.
+struct BatchEnd {
+    const uint32_t *srcs;
+    uint32_t first, cnt;
+    const uint32_t *counts;
+    uint32_t *deg_list, *deg_full;
+    const uint32_t *qbase;
+    uint32_t n;
+    const uint32_t *qcnt;
+    uint32_t levels;
+    uint64_t *vis;
+    uint64_t *frt[3];
+    uint32_t *fnz;
+    uint32_t fnz_words;
+    int W;
+    // counter set of the next batch
+    uint32_t *nwork, *nqcnt, *nhcnt, *ncounts;
+    unsigned long long *nqdeg;
+    uint32_t nq, ncounts_len;
+};
+
+__global__ void batch_end_kernel(BatchEnd b) {
+    const size_t gt = (size_t)blockIdx.x * blockDim.x + threadIdx.x, gs = (size_t)gridDim.x * blockDim.x;
+    for (size_t l = gt; l < b.cnt; l += gs) {
+        const uint32_t d = b.counts[l];
+        if (b.deg_full) {
+            const uint32_t s = b.srcs ? b.srcs[b.first + l] : b.first + (uint32_t)l;
+            b.deg_full[s] = d;
+        } else if (b.deg_list) {
+            b.deg_list[b.first + l] = d;
+        }
+    }
+    const int W = b.W;
+    for (uint32_t j = 0; j <= b.levels; ++j) {
+        const uint32_t c = b.qcnt[j];
+        const uint32_t *q = b.qbase + (size_t)j * b.n;
+        const bool recent = j + 1 >= b.levels;
+        uint64_t *buf = b.frt[j % 3];
+        uint32_t *fz = b.fnz + (size_t)(j % 3) * b.fnz_words;
+        for (size_t i = gt; i < (size_t)c * W; i += gs) {
+            const size_t at = (size_t)q[i / W] * W + (i % W);
+            b.vis[at] = 0;
+            if (recent) buf[at] = 0;
+        }
+        if (recent)
+            for (size_t i = gt; i < c; i += gs) fz[q[i] >> 5] = 0;
+    }
+    for (size_t i = gt; i < b.nq; i += gs) {
+        b.nwork[i] = 0;
+        b.nqcnt[i] = 0;
+        b.nhcnt[i] = 0;
+        b.nqdeg[i] = 0;
+    }
+    for (size_t i = gt; i < b.ncounts_len; i += gs) b.ncounts[i] = 0;
 }
 
 // d = number of vertices other than the source that its lane reached.
@@ -190,8 +236,8 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
         (rc = ws_get(ctx, WS_FNZ, (size_t)fnz_words * 3 * 4, &fnz)) ||
         (rc = ws_get(ctx, WS_HACC, ((size_t)g->n_heavy + 1) * maxW * 8, &hacc)) ||
         (rc = ws_get(ctx, WS_HDONE, ((size_t)g->n_heavy + 1) * 4, &hdone)) ||
-        (rc = ws_get(ctx, WS_COUNTS, (size_t)64 * kMaxWidth * 4, &counts)) ||
-        (rc = ws_get(ctx, WS_MISC, (size_t)nq * 24 + 64, &misc)) ||
+        (rc = ws_get(ctx, WS_COUNTS, (size_t)2 * 64 * kMaxWidth * 4, &counts)) ||
+        (rc = ws_get(ctx, WS_MISC, (size_t)2 * (nq * 24 + 64), &misc)) ||
         (rc = ws_get(ctx, WS_BQUEUE, (size_t)nq * n * 4 + 4, &queues)) ||
         (rc = ws_get(ctx, WS_HQUEUE, (size_t)nq * hq_len * 8, &hqueues)) ||
         (rc = ws_get(ctx, WS_QPTRS, (size_t)nq * 8, &qptrs)))
@@ -200,11 +246,20 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
     if (te_full && (rc = ws_get(ctx, WS_TE, (size_t)64 * kMaxWidth * 8, &te))) return rc;
     uint64_t *frt[3] = {(uint64_t *)f0, (uint64_t *)f1, (uint64_t *)f2};
     uint32_t *fnzp = (uint32_t *)fnz;
-    // misc: qdeg[nq] (u64), then work[nq], qcnt[nq], hcnt[nq] (u32)
-    unsigned long long *qdeg = (unsigned long long *)misc;
-    uint32_t *work = (uint32_t *)(qdeg + nq);
-    uint32_t *qcnt = work + nq;
-    uint32_t *hcnt = qcnt + nq;
+    // Two counter sets, used by alternate batches (the end of a batch zeros
+    // the other): misc = [set 0: qdeg[nq] (u64), work, qcnt, hcnt (u32)]
+    // then set 1; counts = per-lane totals of set 0 then set 1.
+    unsigned long long *qdeg_s[2];
+    uint32_t *work_s[2], *qcnt_s[2], *hcnt_s[2], *counts_s[2];
+    for (int ps = 0; ps < 2; ++ps) {
+        qdeg_s[ps] = (unsigned long long *)((char *)misc + (size_t)ps * (nq * 24 + 64));
+        work_s[ps] = (uint32_t *)(qdeg_s[ps] + nq);
+        qcnt_s[ps] = work_s[ps] + nq;
+        hcnt_s[ps] = qcnt_s[ps] + nq;
+        counts_s[ps] = (uint32_t *)counts + (size_t)ps * 64 * kMaxWidth;
+    }
+    unsigned long long *qdeg = qdeg_s[0];
+    uint32_t *work = work_s[0], *qcnt = qcnt_s[0], *hcnt = hcnt_s[0];
     uint32_t *qbase = (uint32_t *)queues;
     uint64_t *hqbase = (uint64_t *)hqueues;
     auto Q = [&](uint32_t j) { return qbase + (size_t)j * n; };
@@ -228,12 +283,17 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
         if (e != hipSuccess) return check_hip(ctx, e, "queue table upload");
     }
 
-    for (uint32_t first = 0; first < nsrc;) {
+    hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, st, work_s[0], qcnt_s[0], hcnt_s[0], qdeg_s[0],
+                       (int)nq, counts_s[0], 64 * kMaxWidth);
+    for (uint32_t first = 0, parity = 0; first < nsrc; parity ^= 1u) {
         const uint32_t remaining = nsrc - first;
         const int W = width_for(remaining, maxW);
         const uint32_t cnt = remaining < (uint32_t)(64 * W) ? remaining : (uint32_t)(64 * W);
-        hipLaunchKernelGGL(batch_reset_kernel, dim3(1), dim3(256), 0, st, work, qcnt, hcnt, qdeg, (int)nq,
-                           (uint32_t *)counts, 64 * W);
+        qdeg = qdeg_s[parity];
+        work = work_s[parity];
+        qcnt = qcnt_s[parity];
+        hcnt = hcnt_s[parity];
+        counts = counts_s[parity];
         hipLaunchKernelGGL(batch_seed_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, srcs, first,
                            cnt, W, alive, g->row_ptr, (uint64_t *)vis, frt[0], fnzp, F(0));
         for (uint32_t lev = 1; lev <= levels; ++lev) {
@@ -298,20 +358,32 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
             }
             hipLaunchKernelGGL(te_scatter_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, srcs, first,
                                cnt, (const unsigned long long *)tep, te_full);
-        } else {
-            hipLaunchKernelGGL(batch_scatter_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, srcs,
-                               first, cnt, (const uint32_t *)counts, deg_list, scatter ? deg_full : nullptr);
         }
-        // Clean up: vis rows of every list, the last two frontier buffers
-        // and maps (older ones were cleared by the levels themselves).
+        BatchEnd be;
+        be.srcs = srcs;
+        be.first = first;
+        be.cnt = te_full ? 0u : cnt;
+        be.counts = (const uint32_t *)counts;
+        be.deg_list = scatter ? nullptr : deg_list;
+        be.deg_full = scatter ? deg_full : nullptr;
+        be.qbase = qbase;
+        be.n = n;
+        be.qcnt = qcnt;
+        be.levels = levels;
+        be.vis = (uint64_t *)vis;
+        for (int i = 0; i < 3; ++i) be.frt[i] = frt[i];
+        be.fnz = fnzp;
+        be.fnz_words = fnz_words;
+        be.W = W;
+        be.nwork = work_s[parity ^ 1u];
+        be.nqcnt = qcnt_s[parity ^ 1u];
+        be.nhcnt = hcnt_s[parity ^ 1u];
+        be.nqdeg = qdeg_s[parity ^ 1u];
+        be.ncounts = counts_s[parity ^ 1u];
+        be.nq = nq;
+        be.ncounts_len = 64u * kMaxWidth;
         const int prec = prof_begin(ctx, 0, 0.0);
-        const int cgrid = ctx->num_cu * 4;
-        for (uint32_t j = 0; j <= levels; ++j)
-            hipLaunchKernelGGL(clear_rows_kernel, dim3(cgrid), dim3(256), 0, st, Q(j), qcnt + j,
-                               (uint64_t *)vis, W, (uint32_t *)nullptr);
-        for (uint32_t j = (levels >= 1 ? levels - 1 : 0); j <= levels; ++j)
-            hipLaunchKernelGGL(clear_rows_kernel, dim3(cgrid), dim3(256), 0, st, Q(j), qcnt + j,
-                               frt[j % 3], W, fnzp + (size_t)(j % 3) * fnz_words);
+        hipLaunchKernelGGL(batch_end_kernel, dim3(ctx->num_cu * 4), dim3(256), 0, st, be);
         prof_end(ctx, prec);
         first += cnt;
     }

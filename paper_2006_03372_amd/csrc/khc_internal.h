@@ -152,6 +152,7 @@ enum WsSlot {
     WS_APPROX_SCAL,
     WS_APPROX_X,
     WS_APPROX_Y,
+    WS_MINPART,
     WS_NUM_SLOTS
 };
 

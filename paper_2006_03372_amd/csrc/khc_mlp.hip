@@ -140,16 +140,22 @@ __global__ __launch_bounds__(256) void mlp_forward_kernel(const float *X, uint32
     }
 }
 
-// Gradient of L = sum over the batch rows of (y - target)^2 / batch, for
-// rows ridx[first .. first+count).  Per-wave accumulators (MFMA fragments
-// for dW2 and dW1) are flushed to grad (fp32) with atomics at the end.
+// Per-block partial gradient of L = sum over the batch rows of
+// (y - target)^2 / batch, for rows ridx[first .. first+count).  Per-wave
+// accumulators (MFMA fragments for dW2 and dW1) are summed over the block's
+// waves in wave order in LDS and written to part[blockIdx.x][0 .. kParams)
+// with the block's loss at index kParams; reduce_kernel sums the blocks in
+// block order, so a training run is reproducible bit for bit.
+constexpr int kPartStride = kParams + 1;
+constexpr int kMaxGradBlocks = 256;
+
 __global__ __launch_bounds__(256) void mlp_backward_kernel(const float *X, const float *target,
                                                            const uint32_t *ridx, uint32_t first,
                                                            uint32_t count, const float *params,
-                                                           const short *copies, float *grad,
-                                                           float *loss) {
+                                                           const short *copies, float *part) {
     __shared__ TileLds lds[kWaves];
     __shared__ short w2t[kHid][kHid + 4];  // W2 in bf16, [o][i]
+    __shared__ float bsum[kPartStride];
     const int wave = threadIdx.x >> 6, lane = threadIdx.x & 63, r = lane & 15, q = lane >> 4;
     for (int e = threadIdx.x; e < kHid * kHid; e += blockDim.x) w2t[e / kHid][e % kHid] = copies[cW2 + e];
     __syncthreads();
@@ -242,20 +248,43 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(const float *X, const
         __builtin_amdgcn_s_waitcnt(0);
         __builtin_amdgcn_wave_barrier();
     }
-    // flush: D layout d[i] = G[16 tm + 4q + i][16 tn + r]
-    for (int tm = 0; tm < 4; ++tm) {
-        for (int tn = 0; tn < 4; ++tn)
-            for (int i = 0; i < 4; ++i)
-                atomicAdd(&grad[oW2 + (16 * tm + 4 * q + i) * kHid + 16 * tn + r], gW2[tm][tn][i]);
-        if (r < kIn)
-            for (int i = 0; i < 4; ++i) atomicAdd(&grad[oW1 + (16 * tm + 4 * q + i) * kIn + r], gW1[tm][i]);
-    }
-    atomicAdd(&grad[ob1 + lane], gb1);
-    atomicAdd(&grad[ob2 + lane], gb2);
-    atomicAdd(&grad[oW3 + lane], gW3);
-    if (lane == 0) atomicAdd(&grad[ob3], gb3);
     for (int off = 32; off > 0; off >>= 1) lsum += __shfl_xor(lsum, off, 64);
-    if (lane == 0 && loss) atomicAdd(loss, lsum);
+    // block sum in wave order; D layout d[i] = G[16 tm + 4q + i][16 tn + r]
+    for (int w = 0; w < kWaves; ++w) {
+        __syncthreads();
+        if (wave != w) continue;
+        const bool set = w == 0;
+        auto put = [&](int idx, float v) { bsum[idx] = set ? v : bsum[idx] + v; };
+        for (int tm = 0; tm < 4; ++tm) {
+            for (int tn = 0; tn < 4; ++tn)
+                for (int i = 0; i < 4; ++i) put(oW2 + (16 * tm + 4 * q + i) * kHid + 16 * tn + r, gW2[tm][tn][i]);
+            if (r < kIn)
+                for (int i = 0; i < 4; ++i) put(oW1 + (16 * tm + 4 * q + i) * kIn + r, gW1[tm][i]);
+        }
+        put(ob1 + lane, gb1);
+        put(ob2 + lane, gb2);
+        put(oW3 + lane, gW3);
+        if (lane == 0) {
+            put(ob3, gb3);
+            put(kParams, lsum);
+        }
+    }
+    __syncthreads();
+    float *out = part + (size_t)blockIdx.x * kPartStride;
+    for (int i = threadIdx.x; i < kPartStride; i += blockDim.x) out[i] = bsum[i];
+}
+
+// grad[i] = sum over blocks b (in order) of part[b][i]; the loss entry is
+// added to *loss when accumulate is set, else stored.
+__global__ void reduce_kernel(const float *part, int nblocks, float *grad, float *loss, int accumulate) {
+    const int i = blockIdx.x * blockDim.x + threadIdx.x;
+    if (i >= kPartStride) return;
+    float acc = 0.f;
+    for (int b = 0; b < nblocks; ++b) acc += part[(size_t)b * kPartStride + i];
+    if (i < kParams)
+        grad[i] = acc;
+    else
+        *loss = accumulate ? *loss + acc : acc;
 }
 
 // Adam on the fp32 parameters, then refresh the bf16 copies and zero the
@@ -301,6 +330,7 @@ struct khc_mlp {
     float *m = nullptr, *v = nullptr;
     short *copies = nullptr;  // bf16
     float *loss = nullptr;
+    float *part = nullptr;  // per-block partial gradients [kMaxGradBlocks][kPartStride]
     uint32_t *perm = nullptr;
     size_t perm_len = 0;
     uint64_t step = 0;
@@ -331,7 +361,8 @@ int khc_mlp_create(khc_ctx *ctx, uint64_t seed, khc_mlp **out) {
     const size_t fb = kParams * sizeof(float);
     if (hipMalloc(&m->params, fb) != hipSuccess || hipMalloc(&m->grad, fb) != hipSuccess ||
         hipMalloc(&m->m, fb) != hipSuccess || hipMalloc(&m->v, fb) != hipSuccess ||
-        hipMalloc(&m->copies, kCopies * sizeof(short)) != hipSuccess || hipMalloc(&m->loss, 64) != hipSuccess) {
+        hipMalloc(&m->copies, kCopies * sizeof(short)) != hipSuccess || hipMalloc(&m->loss, 64) != hipSuccess ||
+        hipMalloc(&m->part, (size_t)kMaxGradBlocks * kPartStride * sizeof(float)) != hipSuccess) {
         (void)hipGetLastError();
         khc_mlp_destroy(m);
         return set_error(ctx, KHC_ENOMEM, "mlp allocation failed");
@@ -360,7 +391,7 @@ int khc_mlp_destroy(khc_mlp *m) {
     if (!m) return KHC_EINVAL;
     if (m->ctx) (void)hipStreamSynchronize(m->ctx->stream);
     for (void *p : {(void *)m->params, (void *)m->grad, (void *)m->m, (void *)m->v, (void *)m->copies,
-                    (void *)m->loss, (void *)m->perm})
+                    (void *)m->loss, (void *)m->part, (void *)m->perm})
         if (p) (void)hipFree(p);
     delete m;
     return KHC_OK;
@@ -408,13 +439,13 @@ int khc_mlp_gradient(khc_ctx *ctx, khc_mlp *m, const float *X, const float *targ
     if (!ctx) return KHC_EINVAL;
     if (!m || !n || !X || !target) return set_error(ctx, KHC_EINVAL, "null argument or empty batch");
     hipStream_t st = ctx->stream;
-    hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(256), 0, st, m->grad, kParams);
-    hipLaunchKernelGGL(zero_f32_kernel, dim3(1), dim3(64), 0, st, m->loss, 1);
     const uint32_t tiles = (n + 15) / 16;
     uint32_t grid = (tiles + kWaves - 1) / kWaves;
-    if (grid > (uint32_t)ctx->num_cu * 4) grid = ctx->num_cu * 4;
+    if (grid > (uint32_t)kMaxGradBlocks) grid = kMaxGradBlocks;
     hipLaunchKernelGGL(mlp_backward_kernel, dim3(grid), dim3(256), 0, st, X, target, (const uint32_t *)nullptr,
-                       0u, n, m->params, m->copies, m->grad, m->loss);
+                       0u, n, m->params, m->copies, m->part);
+    hipLaunchKernelGGL(reduce_kernel, dim3((kPartStride + 255) / 256), dim3(256), 0, st, (const float *)m->part,
+                       (int)grid, m->grad, m->loss, 0);
     float l = 0.f;
     hipError_t e = hipMemcpyAsync(&l, m->loss, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -455,7 +486,9 @@ int khc_mlp_train(khc_ctx *ctx, khc_mlp *m, const float *X, const float *target,
             uint32_t grid = (tiles + kWaves - 1) / kWaves;
             if (grid > 64) grid = 64;
             hipLaunchKernelGGL(mlp_backward_kernel, dim3(grid), dim3(256), 0, st, X, target,
-                               (const uint32_t *)m->perm, first, cnt, m->params, m->copies, m->grad, m->loss);
+                               (const uint32_t *)m->perm, first, cnt, m->params, m->copies, m->part);
+            hipLaunchKernelGGL(reduce_kernel, dim3((kPartStride + 255) / 256), dim3(256), 0, st,
+                               (const float *)m->part, (int)grid, m->grad, m->loss, 1);
             m->step++;
             const float c1 = 1.f - std::pow(b1, (float)m->step), c2 = 1.f - std::pow(b2, (float)m->step);
             hipLaunchKernelGGL(adam_kernel, dim3(1), dim3(256), 0, st, m->params, m->grad, m->m, m->v, m->copies,
