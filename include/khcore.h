@@ -173,6 +173,8 @@ int khdeg_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, u
  * h-degree is at most the level k = max(k, min live h-degree), gives it
  * core k, and recomputes the h-degree of the live vertices within h hops
  * of the removed ones (Algorithms 1-2, Observations 1-2).
+ *   h           1..1024 (1..32 with the persistent driver and for graphs
+ *               made by khc_graph_create_batched); otherwise KHC_EINVAL
  *   core        device uint32[n] output (isolated vertices: 0)
  *   peel_round  device uint32[n] output or NULL: round of removal
  *   stats       host struct or NULL

@@ -271,7 +271,7 @@ int khc_create(khc_ctx **out, int device, void *hip_stream) {
     if (hipDeviceGetAttribute(&rate_khz, hipDeviceAttributeWallClockRate, device) == hipSuccess && rate_khz > 0)
         c->wall_clock_khz = (uint64_t)rate_khz;
     (void)hipGetLastError();
-    if (hipHostMalloc((void **)&c->host_scalars, 256, hipHostMallocDefault) != hipSuccess) {
+    if (hipHostMalloc((void **)&c->host_scalars, kHostScalarBytes, hipHostMallocDefault) != hipSuccess) {
         delete c;
         return KHC_ENOMEM;
     }
@@ -567,6 +567,11 @@ int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
     gr->row_ptr = g->row_ptr;
     gr->col = g->col;
     gr->n_light = (uint32_t)light.size();
+    for (uint32_t v : light) {
+        const uint64_t d = rp[v + 1] - rp[v];
+        gr->n_light_mid += d > kMidDeg;
+        gr->n_light_nz += d > 0;
+    }
     gr->n_heavy = (uint32_t)heavy.size();
     gr->n_chunks = (uint32_t)chunk_heavy.size();
     gr->max_degree = maxdeg;

@@ -211,22 +211,25 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
         return KHC_OK;
     }
     hipStream_t st = ctx->stream;
-    const int nscal = R_CNT + (int)h + 2;
+    const int nscal = round_nscal(h);
     int rc;
-    void *alive_v, *mark_v, *queue_v, *scal_v, *dhat_v, *lb_v, *ub_v, *x_v, *y_v, *dj_v, *part_v;
+    void *alive_v, *mark_v, *queue_v, *scal_v, *dhat_v, *lb_v, *ub_v, *x_v, *y_v, *dj_v, *part_v, *items_v;
     if ((rc = ws_get(ctx, WS_ALIVE, (size_t)n + 8, &alive_v)) || (rc = ws_get(ctx, WS_MARK, (size_t)n * 4 + 8, &mark_v)) ||
         (rc = ws_get(ctx, WS_QUEUE0, (size_t)n * 4 + 8, &queue_v)) ||
-        (rc = ws_get(ctx, WS_SCRATCH, (size_t)nscal * 4 + (size_t)(h + 2) * 8 + 64, &scal_v)) ||
+        (rc = ws_get(ctx, WS_SCRATCH, round_scalar_bytes(h), &scal_v)) ||
         (rc = ws_get(ctx, WS_DEG, (size_t)n * 4 + 8, &dhat_v)) || (rc = ws_get(ctx, WS_LB, (size_t)n * 4 + 8, &lb_v)) ||
         (rc = ws_get(ctx, WS_DHM1, (size_t)n * 4 + 8, &ub_v)) ||
         (rc = ws_get(ctx, WS_APPROX_X, (size_t)n * kFeat * 4 + 32, &x_v)) ||
         (rc = ws_get(ctx, WS_APPROX_Y, (size_t)n * 4 + 8, &y_v)) ||
         (rc = ws_get(ctx, WS_APPROX_DJ, (size_t)(h - 1) * n * 4 + 4, &dj_v)) ||
-        (rc = ws_get(ctx, WS_MINPART, (size_t)kMinBlocks * 4, &part_v)))
+        (rc = ws_get(ctx, WS_MINPART, (size_t)kMinBlocks * 4, &part_v)) ||
+        (rc = ws_get(ctx, WS_ITEMS, round_item_capacity(n, g->nnz) * sizeof(uint2), &items_v)))
         return rc;
     uint8_t *alive = (uint8_t *)alive_v;
     uint32_t *mark = (uint32_t *)mark_v, *queue = (uint32_t *)queue_v, *scal = (uint32_t *)scal_v;
-    unsigned long long *s64 = (unsigned long long *)((char *)scal_v + (((size_t)nscal * 4 + 63) / 64) * 64);
+    unsigned long long *s64 = round_s64(scal_v, h);
+    uint2 *items = (uint2 *)items_v;
+    const RoundGraph rg = round_graph(g);
     uint32_t *part = (uint32_t *)part_v;
     uint32_t *dhat = estimate ? estimate : (uint32_t *)dhat_v;
     uint32_t *lb = (uint32_t *)lb_v, *ub = (uint32_t *)ub_v;
@@ -258,10 +261,11 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
         hipLaunchKernelGGL(keymin_kernel, dim3(kMinBlocks), dim3(256), 0, st, n, alive, (const uint8_t *)nullptr,
                            dhat, (const uint32_t *)nullptr, part, scal, s64, (int)h);
         hipLaunchKernelGGL(select_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr, alive,
-                           (const uint8_t *)nullptr, dhat, part, mark, core, (uint32_t *)nullptr, r, queue, scal, s64);
+                           (const uint8_t *)nullptr, dhat, part, mark, core, (uint32_t *)nullptr, r, queue, scal, s64,
+                           items, (int)h);
         for (uint32_t lev = 1; lev <= h; ++lev)
-            hipLaunchKernelGGL(affected_kernel, dim3(wgrid), dim3(256), 0, st, n, g->nnz, g->row_ptr, g->col, alive,
-                               mark, queue, scal, s64, (int)lev);
+            hipLaunchKernelGGL(affected_kernel, dim3(wgrid), dim3(256), 0, st, rg, alive, mark, queue, scal, s64,
+                               items, (int)lev, (int)h);
         hipLaunchKernelGGL(kill_kernel, dim3(gn), dim3(256), 0, st, queue, scal, alive);
         hipError_t e = hipMemcpyAsync(hs, scal, (size_t)nscal * 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);

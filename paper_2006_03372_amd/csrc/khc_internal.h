@@ -15,7 +15,16 @@ namespace khc {
 // that whole workgroups process; lighter rows go to one lane group each.
 constexpr uint32_t kHeavyRowArcs = 512;
 constexpr uint32_t kChunkArcs = 4096;
+// Light rows with more arcs than this are scanned by lane groups in the
+// affected-set search; the others by one lane each.
+constexpr uint32_t kMidDeg = 16;
+// A lower bound max(d^{h-1}(u), max over neighbours w of d^{h-1}(w)) reads
+// at most this many neighbours of u: any subset of the neighbours still
+// gives a lower bound, and hub rows stay cheap.
+constexpr uint32_t kLbArcs = 512;
 constexpr int kBlockThreads = 256;  // 4 wavefronts of 64 lanes
+constexpr uint32_t kMaxRoundH = 1024;     // largest h of the host-driven peeling
+constexpr size_t kHostScalarBytes = 16384;  // pinned per-round readback buffer
 constexpr int kMaxWidth = 32;       // uint64 words per vertex per BFS batch
 
 // Lane layout of one vertex row of W uint64 words inside a wavefront:
@@ -95,6 +104,8 @@ struct khc_graph {
     // row schedule (device)
     uint32_t *light_rows = nullptr;  // rows with <= kHeavyRowArcs arcs, by degree descending
     uint32_t n_light = 0;
+    uint32_t n_light_mid = 0;  // light rows with more than kMidDeg arcs (a prefix)
+    uint32_t n_light_nz = 0;   // light rows with at least one arc (a prefix)
     uint32_t *heavy_rows = nullptr;  // heavier rows, by degree descending
     uint32_t n_heavy = 0;
     uint32_t *chunk_heavy = nullptr;  // heavy-row index of each chunk
@@ -153,6 +164,7 @@ enum WsSlot {
     WS_APPROX_X,
     WS_APPROX_Y,
     WS_MINPART,
+    WS_ITEMS,
     WS_NUM_SLOTS
 };
 

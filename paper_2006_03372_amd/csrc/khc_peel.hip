@@ -70,22 +70,33 @@ __global__ void lower_bound_kernel(const uint32_t *list, const uint32_t *s, int 
         end = 0;
         for (int j = 0; j <= h; ++j) end += s[R_CNT + j];
     }
-    const int lane = threadIdx.x & 63;
-    const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
-    const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t i = begin + wave; i < end; i += nwaves) {
-        const uint32_t u = list ? list[i] : i;
-        if (!alive[u]) continue;
-        uint32_t m = 0;
-        for (uint64_t a = row_ptr[u] + lane; a < row_ptr[u + 1]; a += 64) {
-            const uint32_t w = col[a];
-            if (alive[w] && dm[w] > m) m = dm[w];
+    // 16 lanes per vertex, at most kLbArcs neighbours each
+    const int lane = threadIdx.x & 63, sub = lane & 15;
+    const uint32_t grp = (blockIdx.x * blockDim.x + threadIdx.x) >> 4;
+    const uint32_t ngrp = (gridDim.x * blockDim.x) >> 4;
+    const uint32_t span = end - begin;
+    const uint32_t trips = (span + ngrp - 1) / ngrp;
+    for (uint32_t t = 0; t < trips; ++t) {
+        const uint32_t i = begin + t * ngrp + grp;
+        uint32_t m = 0, u = 0;
+        bool live = false;
+        if (i < end) {
+            u = list ? list[i] : i;
+            live = alive[u] != 0;
         }
-        for (int off = 32; off > 0; off >>= 1) {
-            uint32_t o = __shfl_xor(m, off, 64);
+        if (live) {
+            const uint64_t rb = row_ptr[u], re0 = row_ptr[u + 1];
+            const uint64_t re = re0 - rb > kLbArcs ? rb + kLbArcs : re0;
+            for (uint64_t a = rb + sub; a < re; a += 16) {
+                const uint32_t w = col[a];
+                if (alive[w] && dm[w] > m) m = dm[w];
+            }
+        }
+        for (int off = 8; off > 0; off >>= 1) {
+            const uint32_t o = __shfl_xor(m, off, 64);
             m = o > m ? o : m;
         }
-        if (lane == 0) lb[u] = dm[u] > m ? dm[u] : m;
+        if (live && sub == 0) lb[u] = dm[u] > m ? dm[u] : m;
     }
 }
 
@@ -93,6 +104,7 @@ struct PeelState {
     uint8_t *alive, *dirty;
     uint32_t *d, *dm, *lb, *mark, *queue, *list, *s, *part;
     unsigned long long *s64;
+    uint2 *items;
     int nscal;
 };
 
@@ -104,11 +116,12 @@ int peel_round_common(khc_ctx *ctx, const khc_graph *g, uint32_t h, const PeelSt
     const uint32_t n = g->n;
     hipLaunchKernelGGL(select_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr, p.alive,
                        bounded ? p.dirty : (const uint8_t *)nullptr, p.d, p.part, p.mark, core, peel_round, r,
-                       p.queue, p.s, p.s64);
+                       p.queue, p.s, p.s64, p.items, (int)h);
     const int agrid = ctx->num_cu * 4;
+    const RoundGraph rg = round_graph(g);
     for (uint32_t lev = 1; lev <= h; ++lev)
-        hipLaunchKernelGGL(affected_kernel, dim3(agrid), dim3(256), 0, st, n, g->nnz, g->row_ptr, g->col, p.alive,
-                           p.mark, p.queue, p.s, p.s64, (int)lev);
+        hipLaunchKernelGGL(affected_kernel, dim3(agrid), dim3(256), 0, st, rg, p.alive, p.mark, p.queue, p.s, p.s64,
+                           p.items, (int)lev, (int)h);
     hipLaunchKernelGGL(kill_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, p.alive);
     hipError_t e = hipMemcpyAsync(ctx->host_scalars, p.s, (size_t)p.nscal * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -126,6 +139,8 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
                         uint32_t *peel_round, khc_stats *stats) {
     if (g->ngraphs > 1)
         return set_error(ctx, KHC_EINVAL, "graphs packed together need the persistent driver");
+    if (h > kMaxRoundH) return set_error(ctx, KHC_EINVAL, "h above 1024");
+    static_assert((size_t)(R_CNT + 2 * kMaxRoundH + 3) * 4 <= kHostScalarBytes, "round scalars fit the readback");
     const auto t0 = std::chrono::steady_clock::now();
     khc_stats st_local;
     std::memset(&st_local, 0, sizeof(st_local));
@@ -133,9 +148,9 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     hipStream_t st = ctx->stream;
     const bool bounded = ctx->schedule == 1 && h >= 2;
     int rc;
-    void *alive_v, *dirty_v, *d_v, *dm_v, *lb_v, *mark_v, *queue_v, *list_v, *s_v, *part_v;
+    void *alive_v, *dirty_v, *d_v, *dm_v, *lb_v, *mark_v, *queue_v, *list_v, *s_v, *part_v, *items_v;
     PeelState p;
-    p.nscal = R_CNT + (int)h + 2;
+    p.nscal = round_nscal(h);
     if ((rc = ws_get(ctx, WS_ALIVE, (size_t)n + 8, &alive_v)) ||
         (rc = ws_get(ctx, WS_DIRTY, (size_t)n + 8, &dirty_v)) ||
         (rc = ws_get(ctx, WS_DEG, (size_t)n * 4 + 8, &d_v)) ||
@@ -144,8 +159,9 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         (rc = ws_get(ctx, WS_MARK, (size_t)n * 4 + 8, &mark_v)) ||
         (rc = ws_get(ctx, WS_QUEUE0, (size_t)n * 4 + 8, &queue_v)) ||
         (rc = ws_get(ctx, WS_QUEUE1, (size_t)n * 4 + 8, &list_v)) ||
-        (rc = ws_get(ctx, WS_SCRATCH, (size_t)p.nscal * 4 + (size_t)(h + 2) * 8 + 64, &s_v)) ||
-        (rc = ws_get(ctx, WS_MINPART, (size_t)kMinBlocks * 4, &part_v)))
+        (rc = ws_get(ctx, WS_SCRATCH, round_scalar_bytes(h), &s_v)) ||
+        (rc = ws_get(ctx, WS_MINPART, (size_t)kMinBlocks * 4, &part_v)) ||
+        (rc = ws_get(ctx, WS_ITEMS, round_item_capacity(n, g->nnz) * sizeof(uint2), &items_v)))
         return rc;
     p.alive = (uint8_t *)alive_v;
     p.dirty = (uint8_t *)dirty_v;
@@ -156,7 +172,8 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     p.queue = (uint32_t *)queue_v;
     p.list = (uint32_t *)list_v;
     p.s = (uint32_t *)s_v;
-    p.s64 = (unsigned long long *)((char *)s_v + (((size_t)p.nscal * 4 + 63) / 64) * 64);
+    p.s64 = round_s64(s_v, h);
+    p.items = (uint2 *)items_v;
     p.part = (uint32_t *)part_v;
     const int g_n = (int)std::min<uint64_t>(((uint64_t)n + 255) / 256, (uint64_t)ctx->num_cu * 8);
     const int grid_n = g_n < 1 ? 1 : g_n;

@@ -181,24 +181,34 @@ __device__ __forceinline__ uint64_t *frt_buf(const PParams &p, uint32_t i) {
     return i == 0 ? p.frt0 : (i == 1 ? p.frt1 : p.frt2);
 }
 
-// lb(u) = max(dm(u), max over live neighbours of dm); one wavefront per u.
+// lb(u) = max(dm(u), max over live neighbours of dm), the neighbours read
+// limited to the first kLbArcs; 16 lanes per u.
 __device__ void lower_bounds(const PParams &p, const uint32_t *list, uint32_t begin, uint32_t end,
                              bool mark_dirty) {
-    const int lane = threadIdx.x & 63;
-    const size_t wave = gtid() >> 6, nwaves = gstride() >> 6;
-    for (size_t i = begin + wave; i < end; i += nwaves) {
-        const uint32_t u = list ? list[i] : (uint32_t)i;
-        if (!p.alive[u]) continue;
-        uint32_t m = 0;
-        for (uint64_t a = p.row_ptr[u] + lane; a < p.row_ptr[u + 1]; a += 64) {
-            const uint32_t w = p.col[a];
-            if (p.alive[w] && p.dm[w] > m) m = p.dm[w];
+    const int lane = threadIdx.x & 63, sub = lane & 15;
+    const size_t grp = gtid() >> 4, ngrp = gstride() >> 4;
+    const size_t trips = ((size_t)(end - begin) + ngrp - 1) / ngrp;
+    for (size_t t = 0; t < trips; ++t) {
+        const size_t i = begin + t * ngrp + grp;
+        uint32_t m = 0, u = 0;
+        bool live = false;
+        if (i < end) {
+            u = list ? list[i] : (uint32_t)i;
+            live = p.alive[u] != 0;
         }
-        for (int off = 32; off > 0; off >>= 1) {
+        if (live) {
+            const uint64_t rb = p.row_ptr[u], re0 = p.row_ptr[u + 1];
+            const uint64_t re = re0 - rb > kLbArcs ? rb + kLbArcs : re0;
+            for (uint64_t a = rb + sub; a < re; a += 16) {
+                const uint32_t w = p.col[a];
+                if (p.alive[w] && p.dm[w] > m) m = p.dm[w];
+            }
+        }
+        for (int off = 8; off > 0; off >>= 1) {
             const uint32_t o = __shfl_xor(m, off, 64);
             m = o > m ? o : m;
         }
-        if (lane == 0) {
+        if (live && sub == 0) {
             p.lb[u] = p.dm[u] > m ? p.dm[u] : m;
             if (mark_dirty) p.dirty[u] = 1;
         }

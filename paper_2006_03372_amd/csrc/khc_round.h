@@ -8,11 +8,14 @@
 //
 // Round scalars (u32 array s): s[R_K] level, s[R_KNEW] level of this round,
 // s[R_RN] recompute count, s[R_LIVE] live vertices, s[R_CNT + j] vertices put
-// on the queue at BFS level j (level 0 = P); u64 array s64[j]: their total
-// degree.  queue = [P | level 1 | ... | level h].  mark[v] = level + 1 of
-// the level v was queued at (0: not queued).  The minimum key comes from
-// per-block partial minima (kMinBlocks entries) that each consumer reduces
-// itself, so no reset launch is needed between rounds.
+// on the queue at BFS level j (level 0 = P), s[R_CNT + h + 1 + j] push items
+// of level j; u64 array s64[j]: total degree of the level-j vertices.
+// queue = [P | level 1 | ... | level h]; a queued row with more than
+// kPushArcs arcs is also listed as ceil(deg / kPushArcs) push items
+// (row, piece) so that the next level's push splits it over wavefronts.
+// mark[v] = level + 1 of the level v was queued at (0: not queued).  The
+// minimum key comes from per-block partial minima (kMinBlocks entries) that
+// each consumer reduces itself, so no reset launch is needed between rounds.
 #pragma once
 
 #include "khc_internal.h"
@@ -23,6 +26,33 @@ namespace {  // each including source gets its own copy of the kernels
 
 constexpr int kMinBlocks = 1024;
 enum : int { R_K = 0, R_KNEW = 1, R_RN = 2, R_LIVE = 3, R_CNT = 8 };
+constexpr uint32_t kPushArcs = 256;  // arcs per push item
+
+inline int round_nscal(uint32_t h) { return R_CNT + 2 * (int)h + 3; }
+// byte size of the scalar block (u32 scalars, then the u64 degree sums)
+inline size_t round_scalar_bytes(uint32_t h) { return (((size_t)round_nscal(h) * 4 + 63) / 64) * 64 + (size_t)(h + 2) * 8; }
+inline unsigned long long *round_s64(void *s, uint32_t h) {
+    return (unsigned long long *)((char *)s + (((size_t)round_nscal(h) * 4 + 63) / 64) * 64);
+}
+// push items a round can hold: every row's pieces at most once
+inline size_t round_item_capacity(uint32_t n, uint64_t nnz) { return (size_t)(nnz / kPushArcs) + n + 8; }
+
+// The graph as the round kernels read it: CSR plus the row schedule (light
+// rows by descending degree, the first n_mid of them with more than kMidDeg
+// arcs, the first n_nz with at least one; heavy rows cut into chunks).
+struct RoundGraph {
+    uint32_t n;
+    uint64_t nnz;
+    const uint64_t *row_ptr;
+    const uint32_t *col;
+    const uint32_t *light_rows, *heavy_rows, *chunk_heavy, *chunk_first;
+    uint32_t n_mid, n_nz, n_chunks;
+};
+
+inline RoundGraph round_graph(const khc_graph *g) {
+    return RoundGraph{g->n,          g->nnz,         g->row_ptr,   g->col,        g->light_rows, g->heavy_rows,
+                      g->chunk_heavy, g->chunk_first, g->n_light_mid, g->n_light_nz, g->n_chunks};
+}
 
 // Per-block minimum of key(v) = (dirty && dirty[v]) ? lb[v] : d[v] over
 // live v into part[blockIdx.x] (grid must be kMinBlocks).  Block 0 also
@@ -50,6 +80,7 @@ __global__ void keymin_kernel(uint32_t n, const uint8_t *alive, const uint8_t *d
     if (blockIdx.x == 0)
         for (int j = threadIdx.x; j <= h; j += blockDim.x) {
             s[R_CNT + j] = 0;
+            s[R_CNT + h + 1 + j] = 0;
             s64[j] = 0;
             if (j == 0) s[R_RN] = 0;
         }
@@ -82,6 +113,16 @@ __device__ __forceinline__ uint32_t wave_reserve(bool take, uint32_t *counter) {
     return base + (uint32_t)__builtin_popcountll(m & ((1ull << lane) - 1ull));
 }
 
+// List row x (degree deg, queued at level L) as push items when it is heavy.
+__device__ __forceinline__ void add_items(uint32_t x, uint64_t deg, int L, int h, uint32_t *s, uint2 *items) {
+    if (deg <= kPushArcs) return;
+    const uint32_t cnt = (uint32_t)((deg + kPushArcs - 1) / kPushArcs);
+    uint32_t base = 0;
+    for (int j = 0; j < L; ++j) base += s[R_CNT + h + 1 + j];
+    base += atomicAdd(&s[R_CNT + h + 1 + L], cnt);
+    for (uint32_t c = 0; c < cnt; ++c) items[base + c] = make_uint2(x, c);
+}
+
 // Dirty live vertices whose lower bound reached the level.
 [[maybe_unused]] __global__ void collect_kernel(uint32_t n, const uint8_t *alive, const uint8_t *dirty, const uint32_t *lb,
                                const uint32_t *part, uint32_t *list, uint32_t *s) {
@@ -97,7 +138,7 @@ __device__ __forceinline__ uint32_t wave_reserve(bool take, uint32_t *counter) {
 __global__ void select_kernel(uint32_t n, const uint64_t *row_ptr, const uint8_t *alive, const uint8_t *dirty,
                               const uint32_t *d, const uint32_t *part, uint32_t *mark, uint32_t *core,
                               uint32_t *round, uint32_t r, uint32_t *queue, uint32_t *s,
-                              unsigned long long *s64) {
+                              unsigned long long *s64, uint2 *items, int h) {
     const uint32_t k = block_level(part, s);
     if (blockIdx.x == 0 && threadIdx.x == 0) s[R_KNEW] = k;
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
@@ -108,67 +149,149 @@ __global__ void select_kernel(uint32_t n, const uint64_t *row_ptr, const uint8_t
         if (round) round[v] = r;
         mark[v] = 1;
         queue[at] = v;
-        atomicAdd(&s64[0], (unsigned long long)(row_ptr[v + 1] - row_ptr[v]));
+        const uint64_t dv = row_ptr[v + 1] - row_ptr[v];
+        atomicAdd(&s64[0], (unsigned long long)dv);
+        add_items(v, dv, 0, h, s, items);
+    }
+}
+
+// Queue y at level L (its mark already set): append, add its degree and its
+// push items.  Called by the lanes that take a vertex; wave-aggregated.
+__device__ __forceinline__ void queue_take(bool take, uint32_t y, const RoundGraph &g, int L, int h, uint32_t end,
+                                           uint32_t *queue, uint32_t *s, unsigned long long *s64, uint2 *items) {
+    const uint32_t at = wave_reserve(take, &s[R_CNT + L]);
+    if (take) {
+        queue[end + at] = y;
+        const uint64_t dy = g.row_ptr[y + 1] - g.row_ptr[y];
+        atomicAdd(&s64[L], (unsigned long long)dy);
+        add_items(y, dy, L, h, s, items);
     }
 }
 
 // Level L of the affected-set BFS from P over the live graph (P still
-// live).  Push (one wavefront per queued row of level L-1, atomics on the
-// marks) while that level's rows have few arcs; otherwise pull (one thread
-// per unqueued live vertex, looking for a neighbour of level L-1).
-__global__ void affected_kernel(uint32_t n, uint64_t nnz, const uint64_t *row_ptr, const uint32_t *col,
-                                const uint8_t *alive, uint32_t *mark, uint32_t *queue, uint32_t *s,
-                                unsigned long long *s64, int L) {
-    uint32_t begin = 0;
-    for (int j = 0; j + 1 < L; ++j) begin += s[R_CNT + j];
-    const uint32_t end = begin + s[R_CNT + L - 1];
-    const bool pull = s64[L - 1] * 8ull > nnz;
-    const uint32_t tag = (uint32_t)L + 1u;
-    if (pull) {
-        for (uint32_t y0 = blockIdx.x * blockDim.x; y0 < n; y0 += gridDim.x * blockDim.x) {
-            const uint32_t y = y0 + threadIdx.x;
-            bool take = false;
-            uint64_t dy = 0;
-            if (y < n && alive[y] && mark[y] == 0u) {
-                const uint64_t rb = row_ptr[y], re = row_ptr[y + 1];
-                for (uint64_t a = rb; a < re; ++a) {
-                    if (mark[col[a]] == tag - 1u) {
-                        take = true;
-                        break;
-                    }
-                }
-                dy = re - rb;
-            }
-            const uint32_t at = wave_reserve(take, &s[R_CNT + L]);
-            if (take) {
-                mark[y] = tag;
-                queue[end + at] = y;
-                atomicAdd(&s64[L], (unsigned long long)dy);
-            }
-        }
-        return;
+// live).  Push while the rows of level L-1 have few arcs: light rows of
+// level L-1 by groups of 16 lanes, heavy ones as kPushArcs-arc items by
+// whole wavefronts, marks claimed with compare-and-swap.  Otherwise pull:
+// every unqueued live row looks for a neighbour of level L-1, heavy rows by
+// chunks (one wavefront each), rows above kMidDeg arcs by groups of 8
+// lanes, the rest one lane each, all stopping at the first hit.
+__global__ void affected_kernel(RoundGraph g, const uint8_t *alive, uint32_t *mark, uint32_t *queue, uint32_t *s,
+                                unsigned long long *s64, uint2 *items, int L, int h) {
+    uint32_t begin = 0, ibegin = 0;
+    for (int j = 0; j + 1 < L; ++j) {
+        begin += s[R_CNT + j];
+        ibegin += s[R_CNT + h + 1 + j];
     }
+    const uint32_t end = begin + s[R_CNT + L - 1];
+    const uint32_t iend = ibegin + s[R_CNT + h + 1 + L - 1];
+    const bool pull = s64[L - 1] * 8ull > g.nnz;
+    const uint32_t tag = (uint32_t)L + 1u;
     const int lane = threadIdx.x & 63;
     const uint32_t wave = (blockIdx.x * blockDim.x + threadIdx.x) >> 6;
     const uint32_t nwaves = (gridDim.x * blockDim.x) >> 6;
-    for (uint32_t i = begin + wave; i < end; i += nwaves) {
-        const uint32_t x = queue[i];
-        const uint64_t rb = row_ptr[x], re = row_ptr[x + 1];
-        for (uint64_t a0 = rb; a0 < re; a0 += 64) {
-            const uint64_t a = a0 + lane;
+    if (pull) {
+        const uint32_t mid_units = (g.n_mid + 7) / 8;
+        const uint32_t small_units = (g.n_nz - g.n_mid + 63) / 64;
+        const uint32_t units = g.n_chunks + mid_units + small_units;
+        for (uint32_t u = wave; u < units; u += nwaves) {
             bool take = false;
             uint32_t y = 0;
-            uint64_t dy = 0;
-            if (a < re) {
-                y = col[a];
+            if (u < g.n_chunks) {
+                const uint32_t hr = g.chunk_heavy[u];
+                y = g.heavy_rows[hr];
+                if (alive[y] && mark[y] == 0u) {
+                    const uint64_t re = g.row_ptr[y + 1];
+                    const uint64_t a0 = g.row_ptr[y] + (uint64_t)(u - g.chunk_first[hr]) * kChunkArcs;
+                    const uint64_t a1 = a0 + kChunkArcs < re ? a0 + kChunkArcs : re;
+                    bool found = false;
+                    for (uint64_t b = a0; b < a1; b += 64) {
+                        const uint64_t a = b + lane;
+                        const bool hit = a < a1 && mark[g.col[a]] == tag - 1u;
+                        if (__ballot(hit)) {
+                            found = true;
+                            break;
+                        }
+                    }
+                    take = found && lane == 0 && atomicCAS(&mark[y], 0u, tag) == 0u;
+                }
+            } else if (u < g.n_chunks + mid_units) {
+                const uint32_t grp = lane >> 3, sub = lane & 7;
+                const uint32_t i = (u - g.n_chunks) * 8 + grp;
+                if (i < g.n_mid) {
+                    y = g.light_rows[i];
+                    if (alive[y] && mark[y] == 0u) {
+                        const uint64_t rb = g.row_ptr[y], re = g.row_ptr[y + 1];
+                        bool found = false;
+                        for (uint64_t a0 = rb; a0 < re; a0 += 8) {
+                            const uint64_t a = a0 + sub;
+                            const bool hit = a < re && mark[g.col[a]] == tag - 1u;
+                            if ((__ballot(hit) >> (grp * 8)) & 0xFFull) {
+                                found = true;
+                                break;
+                            }
+                        }
+                        if (found && sub == 0) {
+                            mark[y] = tag;  // the group is the only reader of row y
+                            take = true;
+                        }
+                    }
+                }
+            } else {
+                const uint32_t i = g.n_mid + (u - g.n_chunks - mid_units) * 64 + lane;
+                if (i < g.n_nz) {
+                    y = g.light_rows[i];
+                    if (alive[y] && mark[y] == 0u) {
+                        const uint64_t rb = g.row_ptr[y], re = g.row_ptr[y + 1];
+                        for (uint64_t a = rb; a < re; ++a)
+                            if (mark[g.col[a]] == tag - 1u) {
+                                take = true;
+                                break;
+                            }
+                        if (take) mark[y] = tag;
+                    }
+                }
+            }
+            queue_take(take, y, g, L, h, end, queue, s, s64, items);
+        }
+        return;
+    }
+    // push: 4 light rows per wavefront (16 lanes each), then the items
+    const uint32_t light_units = (end - begin + 3) / 4;
+    const uint32_t units = light_units + (iend - ibegin);
+    for (uint32_t u = wave; u < units; u += nwaves) {
+        uint64_t a0 = 0, a1 = 0;
+        uint32_t step = 64, off = (uint32_t)lane;
+        if (u < light_units) {
+            const uint32_t i = begin + u * 4 + (lane >> 4);
+            step = 16;
+            off = lane & 15;
+            if (i < end) {
+                const uint32_t x = queue[i];
+                a0 = g.row_ptr[x];
+                a1 = g.row_ptr[x + 1];
+                if (a1 - a0 > kPushArcs) a1 = a0;  // pushed by its items
+            }
+        } else {
+            const uint2 it = items[ibegin + (u - light_units)];
+            const uint64_t rb = g.row_ptr[it.x], re = g.row_ptr[it.x + 1];
+            a0 = rb + (uint64_t)it.y * kPushArcs;
+            a1 = a0 + kPushArcs < re ? a0 + kPushArcs : re;
+        }
+        // same trip count on every lane of the wavefront
+        uint64_t len = a1 - a0, maxlen = len;
+        for (int o = 32; o > 0; o >>= 1) {
+            const uint64_t t = __shfl_xor(maxlen, o, 64);
+            maxlen = t > maxlen ? t : maxlen;
+        }
+        for (uint64_t b = 0; b < maxlen; b += step) {
+            const uint64_t a = a0 + b + off;
+            bool take = false;
+            uint32_t y = 0;
+            if (b + off < len) {
+                y = g.col[a];
                 take = alive[y] && mark[y] == 0u && atomicCAS(&mark[y], 0u, tag) == 0u;
-                if (take) dy = row_ptr[y + 1] - row_ptr[y];
             }
-            const uint32_t at = wave_reserve(take, &s[R_CNT + L]);
-            if (take) {
-                queue[end + at] = y;
-                atomicAdd(&s64[L], (unsigned long long)dy);
-            }
+            queue_take(take, y, g, L, h, end, queue, s, s64, items);
         }
     }
 }

@@ -104,3 +104,32 @@ def test_certificate_rmat14_h3(ctx):
     verts = rng.choice(g.n, size=300, replace=False)
     fail = oracle.certificate(g, 3, c, r, verts)
     assert fail.sum() == 0, fail
+
+
+def _with_hubs(g, hubs, deg, seed):
+    """g plus `hubs` new vertices, each joined to `deg` random vertices of g."""
+    rng = np.random.default_rng(seed)
+    src, dst = synth.edge_list(g)
+    extra_s, extra_d = [src], [dst]
+    for i in range(hubs):
+        nb = rng.choice(g.n, size=deg, replace=False)
+        extra_s.append(np.full(deg, g.n + i))
+        extra_d.append(nb)
+    return synth.from_edges(g.n + hubs, np.concatenate(extra_s), np.concatenate(extra_d))
+
+
+@pytest.mark.parametrize("h", [2, 3])
+def test_multi_chunk_hubs(ctx, h):
+    """Rows longer than one 4096-arc chunk (pulled by several wavefronts,
+    pushed as several items): both drivers and schedules agree, and the
+    certificate holds on sampled vertices and on the hubs."""
+    g = _with_hubs(synth.chung_lu(6000, 4.0, 2.5, seed=3), 2, 5000, seed=4)
+    assert np.diff(g.row_ptr).max() > 4096
+    runs = [_gpu_core(ctx, g, h, s, 16, drv) for drv in (0, 1) for s in (0, 1)]
+    c, r, _ = runs[0]
+    for c2, r2, _ in runs[1:]:
+        assert (c2 == c).all() and (r2 == r).all()
+    rng = np.random.default_rng(1)
+    verts = np.concatenate([rng.choice(g.n, size=200, replace=False), [g.n - 2, g.n - 1]])
+    fail = oracle.certificate(g, h, c, r, verts)
+    assert fail.sum() == 0, fail
