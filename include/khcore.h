@@ -109,6 +109,25 @@ typedef struct {
  * forgets them.  Timing is taken on the context stream with HIP events. */
 int khc_profile_read(khc_ctx *ctx, khc_profile *out, int reset);
 
+/* Progress of long decompositions: the host-driven peeling and the
+ * approximate mode call fn(user, rounds done, vertices removed, current
+ * level) on the calling thread, at most once every interval_ms
+ * milliseconds.  fn == NULL turns reporting off.  The persistent driver
+ * runs as one launch and does not report. */
+typedef void (*khc_progress_fn)(void *user, uint32_t rounds, uint64_t removed, uint32_t level);
+int khc_set_progress(khc_ctx *ctx, khc_progress_fn fn, void *user, uint32_t interval_ms);
+
+/* Phases of the persistent driver (khc_persist_profile_read order). */
+#define KHC_PERSIST_PHASES 17
+/* init, compact, lb_all, keymin, level, collect, clean, select, affected,
+ * kill, lbd, unmark, bfs_reset, bfs_seed, bfs_level, bfs_scatter, done.
+ * With KHC_OPT_PROFILE on, every persistent run adds, per phase, the
+ * wall-clock milliseconds from the previous grid barrier to the end of the
+ * phase's own barrier (as workgroup 0 sees it) and how often it ran.
+ * ms (host double[KHC_PERSIST_PHASES]) and count (host
+ * uint64_t[KHC_PERSIST_PHASES]) may be NULL; reset != 0 clears the sums. */
+int khc_persist_profile_read(khc_ctx *ctx, double *ms, uint64_t *count, int reset);
+
 /* ---- graph store ------------------------------------------------------ */
 
 /* Wrap a device CSR (Section II's G) and build the row schedule used by

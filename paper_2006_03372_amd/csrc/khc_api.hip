@@ -247,6 +247,14 @@ using namespace khc;
 
 extern "C" {
 
+int khc_set_progress(khc_ctx *ctx, khc_progress_fn fn, void *user, uint32_t interval_ms) {
+    if (!ctx) return KHC_EINVAL;
+    ctx->progress_fn = fn;
+    ctx->progress_user = user;
+    ctx->progress_ms = interval_ms;
+    return KHC_OK;
+}
+
 int khc_create(khc_ctx **out, int device, void *hip_stream) {
     if (!out) return KHC_EINVAL;
     *out = nullptr;
@@ -516,6 +524,15 @@ int khcore_decompose_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base,
 }  // extern "C"
 
 namespace khc {
+
+void report_progress(khc_ctx *ctx, std::chrono::steady_clock::time_point *last, uint32_t rounds, uint64_t removed,
+                     uint32_t level) {
+    if (!ctx->progress_fn) return;
+    const auto now = std::chrono::steady_clock::now();
+    if (std::chrono::duration<double, std::milli>(now - *last).count() < (double)ctx->progress_ms) return;
+    *last = now;
+    ctx->progress_fn(ctx->progress_user, rounds, removed, level);
+}
 
 int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
     int rc = check_csr_args(ctx, g);

@@ -256,6 +256,7 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
     uint64_t left = n;
     uint32_t r = 0;
     uint32_t *hs = ctx->host_scalars;
+    auto last_report = std::chrono::steady_clock::now();
     while (left > 0) {
         if ((uint64_t)r > (uint64_t)n) return set_error(ctx, KHC_ELIMIT, "more rounds than vertices");
         hipLaunchKernelGGL(keymin_kernel, dim3(kMinBlocks), dim3(256), 0, st, n, alive, (const uint8_t *)nullptr,
@@ -298,6 +299,7 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
         sl.affected_total += na;
         left -= np;
         ++r;
+        report_progress(ctx, &last_report, r, (uint64_t)n - left, hs[R_KNEW]);
     }
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "approx end");

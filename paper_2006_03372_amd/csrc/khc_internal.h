@@ -4,6 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <chrono>
 #include <string>
 #include <vector>
 
@@ -83,15 +84,21 @@ struct khc_ctx {
     struct PersistGraph {
         const khc_graph *g;
         uint32_t h;
-        int W, grid, bounded;
+        int W, grid, bounded, profile;
         uint32_t *core, *round;
         hipGraphExec_t exec;
         bool same_args(const PersistGraph &o) const {
             return g == o.g && h == o.h && W == o.W && grid == o.grid && bounded == o.bounded &&
-                   core == o.core && round == o.round;
+                   profile == o.profile && core == o.core && round == o.round;
         }
     };
     std::vector<PersistGraph> persist_graphs;
+    // progress reports of the host-driven loops
+    khc_progress_fn progress_fn = nullptr;
+    void *progress_user = nullptr;
+    uint32_t progress_ms = 1000;
+    double persist_phase_ms[KHC_PERSIST_PHASES] = {};
+    uint64_t persist_phase_count[KHC_PERSIST_PHASES] = {};
     hipStream_t capture_stream = nullptr;  // private stream the persistent launch is captured on
 };
 
@@ -196,6 +203,9 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
 // Host-driven decomposition (khc_peel.hip).
 int host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core, uint32_t *peel_round,
                    khc_stats *stats);
+// Calls the progress callback when its interval has passed since *last.
+void report_progress(khc_ctx *ctx, std::chrono::steady_clock::time_point *last, uint32_t rounds, uint64_t removed,
+                     uint32_t level);
 // Forget captured persistent launches (their arguments are stale).
 void drop_persist_graphs(khc_ctx *ctx, const khc_graph *only);
 

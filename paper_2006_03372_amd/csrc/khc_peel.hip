@@ -197,6 +197,7 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     uint64_t left = n;
     uint32_t r = 0;
     uint32_t *hs = ctx->host_scalars;
+    auto last_report = std::chrono::steady_clock::now();
     while (left > 0) {
         if ((uint64_t)r > (uint64_t)n) return set_error(ctx, KHC_ELIMIT, "more rounds than vertices");
         for (;;) {
@@ -248,6 +249,7 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         st_local.affected_total += na;
         left -= np;
         ++r;
+        report_progress(ctx, &last_report, r, (uint64_t)n - left, hs[R_K]);
     }
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "peel end");

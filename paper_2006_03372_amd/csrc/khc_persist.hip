@@ -46,6 +46,9 @@ struct PCtl {
     uint32_t acnt[kMaxPersistH + 2];   // affected BFS: rows appended per level (0: P)
     uint32_t ahcnt[kMaxPersistH + 2];  // heavy-row work items per level
     unsigned long long stat_hrec, stat_hm1, stat_aff, stat_batches;
+    // per phase: wall-clock ticks from the previous barrier to the end of
+    // the phase's own barrier, and how often it ran (workgroup 0's view)
+    unsigned long long phase_ticks[KHC_PERSIST_PHASES], phase_count[KHC_PERSIST_PHASES];
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
@@ -81,6 +84,7 @@ struct PParams {
     uint32_t ngraphs;
     uint32_t h;
     int bounded;
+    int profile;  // time the phases (KHC_OPT_PROFILE)
     // peeling state
     uint8_t *alive, *dirty;
     uint32_t *d, *dm, *lb, *mark, *queue, *list, *core, *round;
@@ -296,6 +300,7 @@ enum Phase : int {
     PH_BFS_SCATTER,
     PH_DONE
 };
+static_assert((int)PH_DONE + 1 == KHC_PERSIST_PHASES, "phase count of the profile");
 
 // A bounded-BFS job: h-degrees (levels hops) of srcs[0..n) into out[], then
 // continue with phase ret.
@@ -327,6 +332,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
         return cnt ? (int)PH_BFS_RESET : ret;
     };
 
+    uint64_t t_prev = wall_clock64();
     for (;;) {
         // ------------------------------------------------------------ work
         switch (phase) {
@@ -352,6 +358,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                     ctl->abort_reason = 0;
                     for (int i = 0; i < kMaxPersistH + 2; ++i) ctl->acnt[i] = ctl->ahcnt[i] = 0;
                     ctl->stat_hrec = ctl->stat_hm1 = ctl->stat_aff = ctl->stat_batches = 0;
+                    for (int i = 0; i < KHC_PERSIST_PHASES; ++i) ctl->phase_ticks[i] = ctl->phase_count[i] = 0;
                 }
                 break;
             case PH_COMPACT:
@@ -567,6 +574,12 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 break;
         }
         if (!grid_sync(p.sync, &s_gen, &s_ok)) return;
+        if (p.profile && gtid() == 0) {
+            const uint64_t t = wall_clock64();
+            ctl->phase_ticks[phase] += t - t_prev;
+            ctl->phase_count[phase] += 1;
+            t_prev = t;
+        }
 
         // ------------------------------------------------------ next phase
         switch (phase) {
@@ -709,6 +722,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.ngraphs = g->ngraphs;
     p.h = h;
     p.bounded = bounded ? 1 : 0;
+    p.profile = ctx->profile ? 1 : 0;
     p.alive = (uint8_t *)alive;
     p.dirty = (uint8_t *)dirty;
     p.d = (uint32_t *)d;
@@ -759,7 +773,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     hipStream_t st = ctx->stream;
 
     // one graph per argument set, replayed on later calls
-    khc_ctx::PersistGraph key{g, h, W, grid, bounded ? 1 : 0, core, peel_round, nullptr};
+    khc_ctx::PersistGraph key{g, h, W, grid, bounded ? 1 : 0, p.profile, core, peel_round, nullptr};
     hipGraphExec_t exec = nullptr;
     for (auto &e : ctx->persist_graphs)
         if (e.same_args(key)) exec = e.exec;
@@ -797,6 +811,13 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
         return set_error(ctx, KHC_EHIP, "persistent decomposition aborted: a grid barrier wait exceeded " +
                                             std::to_string(ctx->barrier_timeout_s) + " s");
     }
+    if (ctx->profile) {
+        const double ms_per_tick = 1.0 / (double)ctx->wall_clock_khz;
+        for (int i = 0; i < KHC_PERSIST_PHASES; ++i) {
+            ctx->persist_phase_ms[i] += (double)host_ctl.phase_ticks[i] * ms_per_tick;
+            ctx->persist_phase_count[i] += host_ctl.phase_count[i];
+        }
+    }
     if (stats) {
         std::memset(stats, 0, sizeof(*stats));
         stats->rounds = host_ctl.round;
@@ -810,6 +831,23 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     }
     return KHC_OK;
 }
+
+}  // namespace khc
+
+extern "C" int khc_persist_profile_read(khc_ctx *ctx, double *ms, uint64_t *count, int reset) {
+    if (!ctx) return KHC_EINVAL;
+    for (int i = 0; i < KHC_PERSIST_PHASES; ++i) {
+        if (ms) ms[i] = ctx->persist_phase_ms[i];
+        if (count) count[i] = ctx->persist_phase_count[i];
+        if (reset) {
+            ctx->persist_phase_ms[i] = 0.0;
+            ctx->persist_phase_count[i] = 0;
+        }
+    }
+    return KHC_OK;
+}
+
+namespace khc {
 
 void drop_persist_graphs(khc_ctx *ctx, const khc_graph *only) {
     auto &v = ctx->persist_graphs;

@@ -39,7 +39,13 @@ EXPORTED = [
     "khc_graph_create_batched", "khcore_decompose_batched",
     "khc_mlp_create", "khc_mlp_destroy", "khc_mlp_set_params", "khc_mlp_get_params",
     "khc_mlp_forward", "khc_mlp_gradient", "khc_mlp_train", "khc_features", "khcore_decompose_approx",
+    "khc_persist_profile_read", "khc_set_progress",
 ]
+
+PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32)
+
+PERSIST_PHASES = ["init", "compact", "lb_all", "keymin", "level", "collect", "clean", "select", "affected",
+                  "kill", "lbd", "unmark", "bfs_reset", "bfs_seed", "bfs_level", "bfs_scatter", "done"]
 
 N_PARAMS = 4801
 
@@ -114,6 +120,8 @@ def load_library(path: str = LIB_PATH):
         "khc_mlp_train": ([P, P, P, P, u32, u32, u32, ctypes.c_float, u64, P], i32),
         "khc_features": ([P, P, P, u32, P, P, P], i32),
         "khcore_decompose_approx": ([P, P, u32, P, P, P, ctypes.POINTER(Stats)], i32),
+        "khc_persist_profile_read": ([P, P, P, i32], i32),
+        "khc_set_progress": ([P, PROGRESS_FN, P, u32], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -163,6 +171,25 @@ class Context:
         p = Profile()
         self._check(self.lib.khc_profile_read(self.handle, ctypes.byref(p), int(reset)))
         return p.as_dict()
+
+    def set_progress(self, fn=None, interval_ms: int = 1000):
+        """fn(rounds, removed, level), called from the decomposition loops at
+        most every interval_ms milliseconds; None turns it off."""
+        if fn is None:
+            self._progress = None
+            self._check(self.lib.khc_set_progress(self.handle, PROGRESS_FN(), None, interval_ms))
+            return
+        self._progress = PROGRESS_FN(lambda _u, r, removed, level: fn(int(r), int(removed), int(level)))
+        self._check(self.lib.khc_set_progress(self.handle, self._progress, None, interval_ms))
+
+    def persist_profile_read(self, reset: bool = True) -> dict:
+        """Per-phase time (ms) and counts of the persistent driver's runs made
+        while OPT_PROFILE is on."""
+        ms = np.zeros(len(PERSIST_PHASES), dtype=np.float64)
+        cnt = np.zeros(len(PERSIST_PHASES), dtype=np.uint64)
+        self._check(self.lib.khc_persist_profile_read(self.handle, ms.ctypes.data_as(ctypes.c_void_p),
+                                                      cnt.ctypes.data_as(ctypes.c_void_p), int(reset)))
+        return {name: (float(ms[i]), int(cnt[i])) for i, name in enumerate(PERSIST_PHASES)}
 
     def close(self):
         if getattr(self, "handle", None):

@@ -133,3 +133,20 @@ def test_multi_chunk_hubs(ctx, h):
     verts = np.concatenate([rng.choice(g.n, size=200, replace=False), [g.n - 2, g.n - 1]])
     fail = oracle.certificate(g, h, c, r, verts)
     assert fail.sum() == 0, fail
+
+
+def test_progress_reports(ctx):
+    """With a zero interval the host-driven loop reports after every round;
+    the last report has every vertex removed."""
+    from paper_2006_03372_amd import khcore
+    g = synth.chung_lu(1500, 8.0, 2.5, seed=5)
+    seen = []
+    ctx.set_progress(lambda r, removed, level: seen.append((r, removed, level)), 0)
+    try:
+        c, r, st = _gpu_core(ctx, g, 2, 1, 16, 0)
+    finally:
+        ctx.set_progress(None)
+    assert len(seen) == st["rounds"]
+    assert [x[0] for x in seen] == list(range(1, st["rounds"] + 1))
+    assert seen[-1][1] == g.n and seen[-1][2] == c.max()
+    assert all(a[1] < b[1] and a[2] <= b[2] for a, b in zip(seen, seen[1:]))
