@@ -91,6 +91,9 @@ const char *khc_last_error(const khc_ctx *ctx);
                                      (8, 16 or 32; default 32)                                        */
 #define KHC_OPT_BARRIER_TIMEOUT 9 /* seconds a grid-barrier wait may take before the persistent kernel
                                      aborts with KHC_EHIP (default 20)                                */
+#define KHC_OPT_ROUND_LIMIT 10    /* stop a decomposition after this many peeling rounds (0 = none,
+                                     default): vertices not removed by then keep core 0; used by
+                                     the autotuner's trial runs                                      */
 int khc_set_option(khc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while KHC_OPT_PROFILE is 1, per kernel class:
@@ -113,7 +116,9 @@ int khc_profile_read(khc_ctx *ctx, khc_profile *out, int reset);
  * approximate mode call fn(user, rounds done, vertices removed, current
  * level) on the calling thread, at most once every interval_ms
  * milliseconds.  fn == NULL turns reporting off.  The persistent driver
- * runs as one launch and does not report. */
+ * runs as one launch: it publishes its round count and removed vertices to
+ * host memory as it goes and the waiting host thread reports them (level
+ * 0: the levels are per graph). */
 typedef void (*khc_progress_fn)(void *user, uint32_t rounds, uint64_t removed, uint32_t level);
 int khc_set_progress(khc_ctx *ctx, khc_progress_fn fn, void *user, uint32_t interval_ms);
 
@@ -211,6 +216,28 @@ int khcore_decompose_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base,
                              const uint32_t *col, uint64_t nnz, uint32_t h, uint32_t *core,
                              uint32_t *peel_round, khc_stats *stats);
 
+/* ---- autotuner --------------------------------------------------------- */
+
+/* Picks the BFS source-block width (uint64 words per vertex, 64 sources
+ * each) and the wavefronts per CU for decompositions of g at h by timing a
+ * trial of each candidate: the decomposition cut after `rounds` peeling
+ * rounds (KHC_OPT_ROUND_LIMIT), run on the driver khcore_decompose would use
+ * for g.  Candidates: widths 8, 16, 32 and 4, 8, 16 wavefronts per CU.  The
+ * fastest candidate is set on ctx (KHC_OPT_MAX_WIDTH or
+ * KHC_OPT_PERSIST_WIDTH, and KHC_OPT_WAVES_PER_CU); every trial is reported
+ * in *out (host, or NULL).  Synchronous; allocates a trial output buffer. */
+#define KHC_TUNE_MAX 16
+typedef struct {
+    uint32_t width_words;              /* chosen width                              */
+    uint32_t waves_per_cu;             /* chosen wavefronts per CU                  */
+    uint32_t persistent;               /* 1: tuned for the persistent driver        */
+    uint32_t candidates;               /* trials run                                */
+    uint32_t cand_width[KHC_TUNE_MAX];
+    uint32_t cand_waves[KHC_TUNE_MAX];
+    double trial_ms[KHC_TUNE_MAX];     /* wall time of each trial                   */
+} khc_tune;
+int khc_autotune(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t rounds, khc_tune *out);
+
 /* ---- learned approximate mode ----------------------------------------- */
 
 /* A small MLP that estimates log-scaled h-degrees from eight cheap features
@@ -227,6 +254,12 @@ int khc_mlp_destroy(khc_mlp *m);
 /* Host float[4801] in/out (also resets the Adam state on set). */
 int khc_mlp_set_params(khc_ctx *ctx, khc_mlp *m, const float *host_params);
 int khc_mlp_get_params(khc_ctx *ctx, const khc_mlp *m, float *host_params, float *host_grad);
+/* Parameters to / from a file: the 8 bytes "KHCMLP01", uint32 4801, then
+ * the 4801 float32 parameters in the order above (little endian).  Loading
+ * resets the Adam state; a file of another shape gives KHC_EINVAL.
+ * Synchronous. */
+int khc_mlp_save(khc_ctx *ctx, const khc_mlp *m, const char *path);
+int khc_mlp_load(khc_ctx *ctx, khc_mlp *m, const char *path);
 /* y[i] = network(X[i][0..8)), X device float[n][8], y device float[n].
  * Asynchronous. */
 int khc_mlp_forward(khc_ctx *ctx, const khc_mlp *m, const float *X, uint32_t n, float *y);

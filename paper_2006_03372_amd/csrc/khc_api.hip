@@ -283,6 +283,16 @@ int khc_create(khc_ctx **out, int device, void *hip_stream) {
         delete c;
         return KHC_ENOMEM;
     }
+    // progress of the persistent kernel, written by the device while it runs
+    if (hipHostMalloc((void **)&c->persist_progress, 64, hipHostMallocMapped | hipHostMallocCoherent) !=
+            hipSuccess ||
+        hipHostGetDevicePointer((void **)&c->persist_progress_dev, (void *)c->persist_progress, 0) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->persist_progress) (void)hipHostFree((void *)c->persist_progress);
+        (void)hipHostFree(c->host_scalars);
+        delete c;
+        return KHC_ENOMEM;
+    }
     *out = c;
     return KHC_OK;
 }
@@ -301,6 +311,7 @@ int khc_destroy(khc_ctx *ctx) {
     }
     for (auto ev : ctx->prof_pool) (void)hipEventDestroy(ev);
     if (ctx->host_scalars) (void)hipHostFree(ctx->host_scalars);
+    if (ctx->persist_progress) (void)hipHostFree((void *)ctx->persist_progress);
     delete ctx;
     return KHC_OK;
 }
@@ -348,6 +359,10 @@ int khc_set_option(khc_ctx *ctx, int option, int64_t value) {
         case KHC_OPT_BARRIER_TIMEOUT:
             if (value < 1 || value > 600) return set_error(ctx, KHC_EINVAL, "barrier timeout must be 1..600 s");
             ctx->barrier_timeout_s = (int)value;
+            return KHC_OK;
+        case KHC_OPT_ROUND_LIMIT:
+            if (value < 0 || value > 0xFFFFFFFFll) return set_error(ctx, KHC_EINVAL, "round limit must be >= 0");
+            ctx->round_limit = (uint32_t)value;
             return KHC_OK;
         default:
             return set_error(ctx, KHC_EINVAL, "unknown option " + std::to_string(option));

@@ -328,6 +328,9 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
             p.n = n;
             p.n_light = g->n_light;
             p.n_chunks = g->n_chunks;
+            p.gid = nullptr;  // one graph, or batched graphs with every lane of every row read
+            p.seg_pfx = nullptr;
+            p.batch_base = 0;
             // algorithmic bytes of a pull level over the whole graph
             const double bytes = alive ? 0.0
                                        : (double)n * (8.0 + 8.0 * W) + (double)g->nnz * (4.0 + 8.0 * W);

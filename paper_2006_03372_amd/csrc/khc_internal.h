@@ -61,6 +61,7 @@ struct khc_ctx {
     uint64_t ws_limit = 0;
     int validate = 1;
     int waves_per_cu = 16;
+    uint32_t round_limit = 0;  // 0: peel to the end
     // workspace
     std::vector<khc::DevBuf> bufs;
     uint64_t ws_bytes = 0;
@@ -85,14 +86,19 @@ struct khc_ctx {
         const khc_graph *g;
         uint32_t h;
         int W, grid, bounded, profile;
+        uint32_t round_limit;
         uint32_t *core, *round;
         hipGraphExec_t exec;
         bool same_args(const PersistGraph &o) const {
             return g == o.g && h == o.h && W == o.W && grid == o.grid && bounded == o.bounded &&
-                   profile == o.profile && core == o.core && round == o.round;
+                   profile == o.profile && round_limit == o.round_limit && core == o.core && round == o.round;
         }
     };
     std::vector<PersistGraph> persist_graphs;
+    // [rounds done, vertices removed] of the running persistent kernel
+    // (coherent pinned host memory the device writes; host and device views)
+    volatile unsigned long long *persist_progress = nullptr;
+    unsigned long long *persist_progress_dev = nullptr;
     // progress reports of the host-driven loops
     khc_progress_fn progress_fn = nullptr;
     void *progress_user = nullptr;
@@ -172,6 +178,7 @@ enum WsSlot {
     WS_APPROX_Y,
     WS_MINPART,
     WS_ITEMS,
+    WS_SEG,
     WS_NUM_SLOTS
 };
 

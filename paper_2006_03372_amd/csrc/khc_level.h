@@ -107,11 +107,37 @@ struct LevelParams {
     uint32_t *hdone;
     uint32_t *work;    // work-item counter of this level
     uint32_t *counts;  // per-lane reached-vertex totals, summed over levels
-    uint64_t nnz;
+    uint64_t nnz;  // arcs the pull direction would read (push/pull choice)
     uint32_t n;
     uint32_t n_light;
     uint32_t n_chunks;
+    // Graph windows (batched graphs; null for one graph): the batch's
+    // sources are grouped by graph, graph g owning source slots
+    // [seg_pfx[g], seg_pfx[g+1]) of the job and this batch the slots
+    // [batch_base, batch_base + 64 W).  A row of graph g can only hold the
+    // lanes of g's sources, so pull reads and writes only those words and
+    // skips rows of graphs without a source in the batch.
+    const uint32_t *gid;
+    const uint32_t *seg_pfx;
+    uint32_t batch_base;
 };
+
+// Words [*w0, *w1] of row y that can hold bits of this batch; false if none.
+template <int W>
+__device__ __forceinline__ bool row_window(const LevelParams &p, uint32_t y, int *w0, int *w1) {
+    if (!p.gid) {
+        *w0 = 0;
+        *w1 = W - 1;
+        return true;
+    }
+    const uint32_t g = p.gid[y];
+    const uint32_t lo = p.seg_pfx[g], hi = p.seg_pfx[g + 1];
+    const uint32_t b0 = p.batch_base, b1 = p.batch_base + 64u * W;
+    if (hi <= b0 || lo >= b1) return false;
+    *w0 = (int)(((lo > b0 ? lo : b0) - b0) >> 6);
+    *w1 = (int)(((hi < b1 ? hi : b1) - 1u - b0) >> 6);
+    return true;
+}
 
 // Add the WPL words of x to the bit-sliced counters (one ripple-carry add
 // per word: plane k holds bit k of every bit position's count).
@@ -377,7 +403,10 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
             // ---- pull, one chunk of a heavy row, whole workgroup ----
             const uint32_t hi = p.chunk_heavy[item];
             const uint32_t y = p.heavy_rows[hi];
-            const bool live = !p.alive || p.alive[y];
+            int w0 = 0, w1 = W - 1;
+            const bool live = (!p.alive || p.alive[y]) && row_window<W>(p, y, &w0, &w1);
+            // this lane's words [lig * WPL, lig * WPL + WPL) meet the window
+            const bool lane_on = lig * WPL + WPL - 1 >= w0 && lig * WPL <= w1;
             if (live) {
                 const uint32_t c0 = p.chunk_first[hi];
                 const uint32_t nch = p.chunk_first[hi + 1] - c0;
@@ -388,24 +417,26 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
 #pragma unroll
                 for (int j = 0; j < WPL; ++j) acc[j] = 0;
                 uint64_t a = b + group;
-                for (; a + (uint64_t)(kUnroll - 1) * GROUPS < e; a += (uint64_t)kUnroll * GROUPS) {
-                    uint32_t xs[kUnroll];
+                if (lane_on) {
+                    for (; a + (uint64_t)(kUnroll - 1) * GROUPS < e; a += (uint64_t)kUnroll * GROUPS) {
+                        uint32_t xs[kUnroll];
 #pragma unroll
-                    for (int u = 0; u < kUnroll; ++u) xs[u] = p.col[a + (uint64_t)u * GROUPS];
-                    uint64_t t[kUnroll][WPL];
+                        for (int u = 0; u < kUnroll; ++u) xs[u] = p.col[a + (uint64_t)u * GROUPS];
+                        uint64_t t[kUnroll][WPL];
 #pragma unroll
-                    for (int u = 0; u < kUnroll; ++u)
-                        load_words<WPL>(p.frt_in + (size_t)xs[u] * W + lig * WPL, t[u]);
+                        for (int u = 0; u < kUnroll; ++u)
+                            load_words<WPL>(p.frt_in + (size_t)xs[u] * W + lig * WPL, t[u]);
 #pragma unroll
-                    for (int u = 0; u < kUnroll; ++u)
+                        for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
-                        for (int j = 0; j < WPL; ++j) acc[j] |= t[u][j];
-                }
-                for (; a < e; a += GROUPS) {
-                    uint64_t t[WPL];
-                    load_words<WPL>(p.frt_in + (size_t)p.col[a] * W + lig * WPL, t);
+                            for (int j = 0; j < WPL; ++j) acc[j] |= t[u][j];
+                    }
+                    for (; a < e; a += GROUPS) {
+                        uint64_t t[WPL];
+                        load_words<WPL>(p.frt_in + (size_t)p.col[a] * W + lig * WPL, t);
 #pragma unroll
-                    for (int j = 0; j < WPL; ++j) acc[j] |= t[j];
+                        for (int j = 0; j < WPL; ++j) acc[j] |= t[j];
+                    }
                 }
 #pragma unroll
                 for (int j = 0; j < WPL; ++j) s_red[group * W + lig * WPL + j] = acc[j];
@@ -437,7 +468,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                 if (finalize && tid < 64) {
                     // wave 0 completes the row: lane t < W owns word t
                     uint64_t nw = 0;
-                    if (tid < W) {
+                    if (tid >= w0 && tid <= w1) {
                         const uint64_t v = p.vis[(size_t)y * W + tid];
                         nw = s_fin[tid] & ~v;
                         if (nw) {
@@ -463,10 +494,14 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                 bool valid = idx < p.n_light;
                 const uint32_t y = valid ? p.light_rows[idx] : 0u;
                 if (valid && p.alive && !p.alive[y]) valid = false;
+                int w0 = 0, w1 = W - 1;
+                if (valid && !row_window<W>(p, y, &w0, &w1)) valid = false;
+                // this lane's words meet the row's window
+                const bool lane_on = valid && lig * WPL + WPL - 1 >= w0 && lig * WPL <= w1;
                 uint64_t acc[WPL];
 #pragma unroll
                 for (int j = 0; j < WPL; ++j) acc[j] = 0;
-                if (valid) {
+                if (lane_on) {
                     const uint64_t rb = p.row_ptr[y], re = p.row_ptr[y + 1];
                     uint64_t a = rb;
                     for (; a + kUnroll <= re; a += kUnroll) {
@@ -490,7 +525,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                     }
                 }
                 uint64_t v[WPL], nw[WPL];
-                if (valid) {
+                if (lane_on) {
                     load_words<WPL>(p.vis + (size_t)y * W + lig * WPL, v);
                 } else {
 #pragma unroll

@@ -20,6 +20,7 @@
 // b2[64], W3[64], b3.  BF16 copies: W1 padded to [64][16], W2 [64][64],
 // W3 padded to [16][64] (row 0 real).
 #include <cmath>
+#include <cstdio>
 #include <cstring>
 #include <random>
 #include <vector>
@@ -36,6 +37,7 @@ constexpr int kIn = 8, kHid = 64;
 constexpr int oW1 = 0, ob1 = oW1 + kHid * kIn, oW2 = ob1 + kHid, ob2 = oW2 + kHid * kHid, oW3 = ob2 + kHid,
               ob3 = oW3 + kHid, kParams = ob3 + 1;
 static_assert(kParams == 4801, "parameter count");
+constexpr char kMlpMagic[8] = {'K', 'H', 'C', 'M', 'L', 'P', '0', '1'};
 // bf16 copies (shorts): W1p [64][16], W2 [64][64], W3p [16][64]
 constexpr int cW1 = 0, cW2 = cW1 + kHid * 16, cW3 = cW2 + kHid * kHid, kCopies = cW3 + 16 * kHid;
 
@@ -421,6 +423,40 @@ int khc_mlp_get_params(khc_ctx *ctx, const khc_mlp *m, float *host_params, float
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "mlp parameter download");
     return KHC_OK;
+}
+
+int khc_mlp_save(khc_ctx *ctx, const khc_mlp *m, const char *path) {
+    if (!ctx) return KHC_EINVAL;
+    if (!m || !path) return set_error(ctx, KHC_EINVAL, "null argument");
+    std::vector<float> p(kParams);
+    int rc = khc_mlp_get_params(ctx, m, p.data(), nullptr);
+    if (rc) return rc;
+    FILE *f = std::fopen(path, "wb");
+    if (!f) return set_error(ctx, KHC_EINVAL, std::string("cannot open ") + path + " for writing");
+    const uint32_t count = kParams;
+    const bool ok = std::fwrite(kMlpMagic, 1, 8, f) == 8 && std::fwrite(&count, 4, 1, f) == 1 &&
+                    std::fwrite(p.data(), 4, kParams, f) == (size_t)kParams;
+    const bool closed = std::fclose(f) == 0;
+    if (!ok || !closed) return set_error(ctx, KHC_EINVAL, std::string("write to ") + path + " failed");
+    return KHC_OK;
+}
+
+int khc_mlp_load(khc_ctx *ctx, khc_mlp *m, const char *path) {
+    if (!ctx) return KHC_EINVAL;
+    if (!m || !path) return set_error(ctx, KHC_EINVAL, "null argument");
+    FILE *f = std::fopen(path, "rb");
+    if (!f) return set_error(ctx, KHC_EINVAL, std::string("cannot open ") + path);
+    char magic[8];
+    uint32_t count = 0;
+    std::vector<float> p(kParams);
+    bool ok = std::fread(magic, 1, 8, f) == 8 && std::memcmp(magic, kMlpMagic, 8) == 0 &&
+              std::fread(&count, 4, 1, f) == 1 && count == (uint32_t)kParams &&
+              std::fread(p.data(), 4, kParams, f) == (size_t)kParams;
+    char extra;
+    if (ok && std::fread(&extra, 1, 1, f) != 0) ok = false;  // trailing bytes
+    std::fclose(f);
+    if (!ok) return set_error(ctx, KHC_EINVAL, std::string(path) + " is not a saved network of this shape");
+    return khc_mlp_set_params(ctx, m, p.data());
 }
 
 int khc_mlp_forward(khc_ctx *ctx, const khc_mlp *m, const float *X, uint32_t n, float *y) {

@@ -23,11 +23,13 @@
 //        lb(u) = max(dm(u), max over live neighbours w of dm(w))
 //    (the closed (h-1)-ball of a neighbour lies inside u's h-ball).  Before
 //    each round the level is k = max(k, min over live v of key(v)), key =
-//    d for clean and lb for dirty vertices; dirty vertices with lb <= k are
-//    recomputed and the step repeats until none is left.  Then every dirty
-//    vertex has d^h >= lb > k and P = {clean live v : d(v) <= k} is exactly
-//    the set the plain schedule removes.  This carries the lower-bound idea
-//    the paper attributes to h-LB (Section III) over to set removal.
+//    d for clean and lb for dirty vertices; dirty vertices with
+//    lb <= k < d are recomputed and the step repeats until none is left
+//    (k only grows while it repeats, since every key is at most the true
+//    h-degree).  Then a dirty vertex either has d^h >= lb > k or
+//    d^h <= d <= k, and P = {live v : d(v) <= k} is exactly the set the
+//    plain schedule removes.  This carries the lower-bound idea the paper
+//    attributes to h-LB (Section III) over to set removal.
 #include <chrono>
 #include <cstring>
 
@@ -198,7 +200,7 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     uint32_t r = 0;
     uint32_t *hs = ctx->host_scalars;
     auto last_report = std::chrono::steady_clock::now();
-    while (left > 0) {
+    while (left > 0 && !(ctx->round_limit && r >= ctx->round_limit)) {
         if ((uint64_t)r > (uint64_t)n) return set_error(ctx, KHC_ELIMIT, "more rounds than vertices");
         for (;;) {
             hipLaunchKernelGGL(keymin_kernel, dim3(kMinBlocks), dim3(256), 0, st, n, p.alive,
@@ -206,7 +208,7 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
             if (!bounded) break;
             // dirty vertices whose lower bound reached the level are recomputed first
             hipLaunchKernelGGL(collect_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, p.alive, p.dirty, p.lb,
-                               p.part, p.list, p.s);
+                               p.d, p.part, p.list, p.s);
             hipError_t e = hipMemcpyAsync(hs, p.s, (size_t)R_CNT * 4, hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) return check_hip(ctx, e, "level readback");

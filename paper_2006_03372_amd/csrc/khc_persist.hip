@@ -26,6 +26,7 @@
 // share BFS batches: the graphs are disjoint, so their lanes never meet.
 #include <chrono>
 #include <cstring>
+#include <thread>
 
 #include "khc_level.h"
 
@@ -85,6 +86,8 @@ struct PParams {
     uint32_t h;
     int bounded;
     int profile;  // time the phases (KHC_OPT_PROFILE)
+    uint32_t round_limit;  // stop after this many rounds (0: none)
+    unsigned long long *progress;  // host-visible [rounds, removed], or null
     // peeling state
     uint8_t *alive, *dirty;
     uint32_t *d, *dm, *lb, *mark, *queue, *list, *core, *round;
@@ -105,6 +108,12 @@ struct PParams {
     size_t hq_len;
     uint32_t *bqcnt, *bhcnt, *bwork;
     unsigned long long *bqdeg;
+    // BFS sources grouped by graph: graph g's sources sit at
+    // list[vbase[g] ...) (seg_cnt[g] of them); seg_pfx is their exclusive
+    // prefix over graphs, computed when a job starts.
+    uint32_t *seg_cnt, *seg_pfx;
+    const uint64_t *vbase;      // graph offsets [ngraphs + 1] (null: one graph)
+    unsigned long long *bnnz;   // arcs of the graphs the current batch covers
     Sync sync;
 };
 
@@ -168,17 +177,68 @@ __device__ __forceinline__ uint32_t graph_of(const PParams &p, uint32_t v) { ret
 __device__ __forceinline__ size_t gtid() { return (size_t)blockIdx.x * blockDim.x + threadIdx.x; }
 __device__ __forceinline__ size_t gstride() { return (size_t)gridDim.x * blockDim.x; }
 
-// Wave-aggregated append of `take` lanes' values to list[base + ...].
-__device__ __forceinline__ void wave_append(bool take, uint32_t v, uint32_t *list, uint32_t *counter,
-                                            uint32_t offset) {
+__device__ __forceinline__ uint32_t seg_base(const PParams &p, uint32_t g) {
+    return p.vbase ? (uint32_t)p.vbase[g] : 0u;
+}
+
+// Append the `take` lanes' vertices to their graphs' segments of p.list and
+// count them in *total (may be null).  Wave-aggregated when the takers
+// share a graph.  Every lane of the wavefront must call it.
+__device__ void seg_append(const PParams &p, bool take, uint32_t v, uint32_t *total) {
     const uint64_t m = __ballot(take);
     if (!m) return;
     const int lane = threadIdx.x & 63;
     const int leader = __builtin_ctzll(m);
-    uint32_t base = 0;
-    if (lane == leader) base = atomicAdd(counter, (uint32_t)__builtin_popcountll(m));
-    base = __shfl(base, leader, 64);
-    if (take) list[offset + base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = v;
+    const uint32_t g = take ? graph_of(p, v) : 0u;
+    const uint32_t gl = __shfl(g, leader, 64);
+    const uint32_t cnt = (uint32_t)__builtin_popcountll(m);
+    if (__ballot(take && g != gl) == 0ull) {
+        uint32_t base = 0;
+        if (lane == leader) base = atomicAdd(&p.seg_cnt[gl], cnt);
+        base = __shfl(base, leader, 64);
+        if (take) p.list[seg_base(p, gl) + base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = v;
+    } else if (take) {
+        p.list[seg_base(p, g) + atomicAdd(&p.seg_cnt[g], 1u)] = v;
+    }
+    if (total && lane == leader) atomicAdd(total, cnt);
+}
+
+// Source slot i of the current job: graph g with seg_pfx[g] <= i < seg_pfx[g+1].
+__device__ __forceinline__ uint32_t job_source(const PParams &p, uint32_t i) {
+    uint32_t lo = 0, hi = p.ngraphs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (p.seg_pfx[mid] <= i) lo = mid;
+        else hi = mid;
+    }
+    return p.list[seg_base(p, lo) + (i - p.seg_pfx[lo])];
+}
+
+// seg_pfx = exclusive prefix of seg_cnt over the graphs (one workgroup).
+__device__ void scan_segments(const PParams &p, uint32_t *s_ws) {
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+    const uint32_t G = p.ngraphs;
+    uint32_t carry = 0;
+    for (uint32_t c0 = 0; c0 < G; c0 += kBlockThreads) {
+        const uint32_t g = c0 + threadIdx.x;
+        const uint32_t x = g < G ? p.seg_cnt[g] : 0u;
+        uint32_t v = x;
+        for (int off = 1; off < 64; off <<= 1) {
+            const uint32_t t = __shfl_up(v, off, 64);
+            if (lane >= off) v += t;
+        }
+        if (lane == 63) s_ws[wave] = v;
+        __syncthreads();
+        uint32_t before = 0, total = 0;
+        for (int w = 0; w < kBlockThreads / 64; ++w) {
+            if (w < wave) before += s_ws[w];
+            total += s_ws[w];
+        }
+        if (g < G) p.seg_pfx[g] = carry + before + v - x;
+        carry += total;
+        __syncthreads();
+    }
+    if (threadIdx.x == 0) p.seg_pfx[G] = carry;
 }
 
 __device__ __forceinline__ uint64_t *frt_buf(const PParams &p, uint32_t i) {
@@ -302,19 +362,20 @@ enum Phase : int {
 };
 static_assert((int)PH_DONE + 1 == KHC_PERSIST_PHASES, "phase count of the profile");
 
-// A bounded-BFS job: h-degrees (levels hops) of srcs[0..n) into out[], then
-// continue with phase ret.
+// A bounded-BFS job: h-degrees (levels hops) of the n sources grouped by
+// graph in p.list into out[] (clearing their dirty flags when clean is
+// set), then continue with phase ret.
 struct Job {
-    const uint32_t *srcs;
     uint32_t n, levels;
     uint32_t *out;
     int ret;
+    bool clean;
 };
 
 template <int W>
 __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams p) {
     __shared__ LevelLds<W> sh;
-    __shared__ uint32_t s_gen, s_ok;
+    __shared__ uint32_t s_gen, s_ok, s_ws[kBlockThreads / 64];
     if (threadIdx.x == 0) s_gen = 0;
     const uint32_t n = p.n, h = p.h;
     const bool bounded = p.bounded != 0;
@@ -324,10 +385,10 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
 
     // uniform control state
     int phase = PH_INIT;
-    Job job{nullptr, 0, 0, nullptr, PH_DONE};
+    Job job{0, 0, nullptr, PH_DONE, false};
     uint32_t batch = 0, lev = 0, aff_l = 0, np = 0, e_hm1 = 0, e_h = 0;
-    auto start_job = [&](const uint32_t *srcs, uint32_t cnt, uint32_t levels, uint32_t *out, int ret) {
-        job = Job{srcs, cnt, levels, out, ret};
+    auto start_job = [&](uint32_t cnt, uint32_t levels, uint32_t *out, int ret, bool clean) {
+        job = Job{cnt, levels, out, ret, clean};
         batch = 0;
         return cnt ? (int)PH_BFS_RESET : ret;
     };
@@ -349,6 +410,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 for (size_t g = gtid(); g < p.ngraphs; g += gstride()) {
                     p.K[g] = 0;
                     p.MIN[g] = 0xFFFFFFFFu;
+                    p.seg_cnt[g] = 0;
                 }
                 if (gtid() == 0) {
                     ctl->left = n;
@@ -366,7 +428,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 for (size_t v0 = gtid() - lane; v0 < n; v0 += gstride()) {
                     const size_t v = v0 + lane;
                     const bool take = v < n && p.row_ptr[v + 1] > p.row_ptr[v];
-                    wave_append(take, (uint32_t)v, p.list, &ctl->nsrc, 0);
+                    seg_append(p, take, (uint32_t)v, &ctl->nsrc);
                 }
                 if (gtid() == 0) {
                     ctl->stat_hrec += n;
@@ -377,11 +439,25 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 lower_bounds(p, nullptr, 0, n, false);
                 break;
             case PH_KEYMIN:
-                for (size_t v = gtid(); v < n; v += gstride()) {
-                    if (!p.alive[v]) continue;
-                    const uint32_t key = (bounded && p.dirty[v]) ? p.lb[v] : p.d[v];
-                    const uint32_t g = graph_of(p, (uint32_t)v);
-                    if (key < p.MIN[g]) atomicMin(&p.MIN[g], key);
+                // per-graph minimum key; a wavefront whose 64 vertices share
+                // a graph (the usual case: graphs are contiguous) reduces first
+                for (size_t v0 = gtid() - lane; v0 < n; v0 += gstride()) {
+                    const size_t v = v0 + lane;
+                    uint32_t key = 0xFFFFFFFFu, g = 0;
+                    if (v < n) {
+                        g = graph_of(p, (uint32_t)v);
+                        if (p.alive[v]) key = (bounded && p.dirty[v]) ? p.lb[v] : p.d[v];
+                    }
+                    const uint32_t g0 = __shfl(g, 0, 64);
+                    if (__ballot(v < n && g != g0) == 0ull) {
+                        for (int off = 32; off > 0; off >>= 1) {
+                            const uint32_t o = __shfl_xor(key, off, 64);
+                            key = o < key ? o : key;
+                        }
+                        if (lane == 0 && key < p.MIN[g0]) atomicMin(&p.MIN[g0], key);
+                    } else if (v < n && key < p.MIN[g]) {
+                        atomicMin(&p.MIN[g], key);
+                    }
                 }
                 break;
             case PH_LEVEL:
@@ -389,6 +465,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                     const uint32_t m = p.MIN[g];
                     if (m != 0xFFFFFFFFu && m > p.K[g]) p.K[g] = m;
                     p.MIN[g] = 0xFFFFFFFFu;
+                    p.seg_cnt[g] = 0;
                 }
                 if (gtid() == 0) {
                     ctl->rn = 0;
@@ -400,23 +477,23 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 for (size_t v0 = gtid() - lane; v0 < n; v0 += gstride()) {
                     const size_t v = v0 + lane;
                     const bool take =
-                        v < n && p.alive[v] && p.dirty[v] && p.lb[v] <= p.K[graph_of(p, (uint32_t)v)];
-                    wave_append(take, (uint32_t)v, p.list, &ctl->rn, 0);
+                        v < n && p.alive[v] && p.dirty[v] && p.lb[v] <= p.K[graph_of(p, (uint32_t)v)] &&
+                        p.d[v] > p.K[graph_of(p, (uint32_t)v)];
+                    seg_append(p, take, (uint32_t)v, &ctl->rn);
                 }
                 break;
-            case PH_CLEAN: {
-                const uint32_t rn = ctl->rn;
-                for (size_t i = gtid(); i < rn; i += gstride()) p.dirty[p.list[i]] = 0;
-                if (gtid() == 0) ctl->stat_hrec += rn;
+            case PH_CLEAN:
+                // the job's scatter cleared the recomputed vertices' dirty flags
+                if (gtid() == 0) ctl->stat_hrec += ctl->rn;
                 break;
-            }
             case PH_SELECT: {
                 // P: clean live vertices at or below their graph's level
                 const uint32_t r = ctl->round;
                 for (size_t v0 = gtid() - lane; v0 < n; v0 += gstride()) {
                     const size_t v = v0 + lane;
                     bool take = false;
-                    if (v < n && p.alive[v] && !(bounded && p.dirty[v])) {
+                    // d is exact when clean and an upper bound when dirty
+                    if (v < n && p.alive[v]) {
                         const uint32_t k = p.K[graph_of(p, (uint32_t)v)];
                         if (p.d[v] <= k) {
                             take = true;
@@ -450,9 +527,24 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                     e_h += ctl->acnt[j];
                 }
                 for (size_t i = gtid(); i < np; i += gstride()) p.alive[p.queue[i]] = 0;
+                {
+                    // sources of the recompute job, grouped by graph
+                    const uint32_t span = (bounded ? e_hm1 : e_h) - np;
+                    for (size_t i0 = gtid() - lane; i0 < span; i0 += gstride()) {
+                        const size_t i = i0 + lane;
+                        const bool take = i < span;
+                        seg_append(p, take, take ? p.queue[np + i] : 0u, nullptr);
+                    }
+                }
                 if (gtid() == 0) {
                     ctl->left -= np;
                     ctl->round += 1;
+                    if (p.progress) {
+                        __hip_atomic_store(&p.progress[0], (unsigned long long)ctl->round, __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                        __hip_atomic_store(&p.progress[1], (unsigned long long)(n - ctl->left), __ATOMIC_RELAXED,
+                                           __HIP_MEMORY_SCOPE_SYSTEM);
+                    }
                     ctl->stat_aff += e_h - np;
                     if (bounded) ctl->stat_hm1 += e_hm1 - np;
                     else ctl->stat_hrec += e_h - np;
@@ -480,6 +572,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                     }
                     for (uint32_t i = threadIdx.x; i < per; i += blockDim.x) p.counts[i] = 0;
                     if (threadIdx.x == 0) ctl->stat_batches++;
+                    if (batch == 0) scan_segments(p, s_ws);
                 }
                 break;
             case PH_BFS_SEED: {
@@ -492,8 +585,18 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 f0.qdeg = p.bqdeg;
                 f0.hq = p.bhq;
                 f0.hcnt = p.bhcnt;
+                if (gtid() == 0) {
+                    // arcs of the graphs this batch covers (sources are grouped by graph)
+                    unsigned long long arcs = p.nnz;
+                    if (p.vbase) {
+                        const uint32_t ga = graph_of(p, job_source(p, first));
+                        const uint32_t gb = graph_of(p, job_source(p, first + cnt - 1));
+                        arcs = p.row_ptr[p.vbase[gb + 1]] - p.row_ptr[p.vbase[ga]];
+                    }
+                    *p.bnnz = arcs;
+                }
                 for (size_t l = gtid(); l < cnt; l += gstride()) {
-                    const uint32_t s = job.srcs[first + l];
+                    const uint32_t s = job_source(p, first + (uint32_t)l);
                     f0.q[l] = s;
                     if (!p.alive[s]) continue;
                     const uint64_t bit = 1ull << (l & 63);
@@ -538,10 +641,13 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 lp.hdone = p.hdone;
                 lp.work = p.bwork + lev;
                 lp.counts = p.counts;
-                lp.nnz = p.nnz;
+                lp.nnz = *p.bnnz;
                 lp.n = n;
                 lp.n_light = p.n_light;
                 lp.n_chunks = p.n_chunks;
+                lp.gid = p.gid;
+                lp.seg_pfx = p.gid ? p.seg_pfx : nullptr;
+                lp.batch_base = batch * per;
                 if (lev == job.levels)
                     level_body<W, true>(lp, sh);
                 else
@@ -552,7 +658,11 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 // results, then clear what the batch touched
                 const uint32_t first = batch * per;
                 const uint32_t cnt = job.n - first < per ? job.n - first : per;
-                for (size_t l = gtid(); l < cnt; l += gstride()) job.out[job.srcs[first + l]] = p.counts[l];
+                for (size_t l = gtid(); l < cnt; l += gstride()) {
+                    const uint32_t s = job_source(p, first + (uint32_t)l);
+                    job.out[s] = p.counts[l];
+                    if (job.clean) p.dirty[s] = 0;
+                }
                 for (uint32_t j = 0; j <= job.levels; ++j) {
                     const uint32_t c = p.bqcnt[j];
                     const uint32_t *q = p.bq + (size_t)j * n;
@@ -585,7 +695,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
         switch (phase) {
             case PH_INIT: phase = PH_COMPACT; break;
             case PH_COMPACT:
-                phase = start_job(p.list, ctl->nsrc, h, p.d, bounded ? (int)PH_LB_ALL : (int)PH_KEYMIN);
+                phase = start_job(ctl->nsrc, h, p.d, bounded ? (int)PH_LB_ALL : (int)PH_KEYMIN, false);
                 // the (h-1)-degrees follow the h-degrees with the same sources
                 break;
             case PH_LB_ALL: phase = ctl->left ? PH_KEYMIN : PH_DONE; break;
@@ -593,7 +703,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
             case PH_LEVEL: phase = bounded ? PH_COLLECT : PH_SELECT; break;
             case PH_COLLECT: {
                 const uint32_t rn = ctl->rn;
-                phase = rn ? start_job(p.list, rn, h, p.d, PH_CLEAN) : (int)PH_SELECT;
+                phase = rn ? start_job(rn, h, p.d, PH_CLEAN, true) : (int)PH_SELECT;
                 break;
             }
             case PH_CLEAN: phase = PH_KEYMIN; break;
@@ -607,12 +717,14 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 break;
             case PH_KILL:
                 if (bounded)
-                    phase = start_job(p.queue + np, e_hm1 - np, h - 1, p.dm, PH_LBD);
+                    phase = start_job(e_hm1 - np, h - 1, p.dm, PH_LBD, false);
                 else
-                    phase = start_job(p.queue + np, e_h - np, h, p.d, PH_UNMARK);
+                    phase = start_job(e_h - np, h, p.d, PH_UNMARK, false);
                 break;
             case PH_LBD:
-            case PH_UNMARK: phase = ctl->left ? PH_KEYMIN : PH_DONE; break;
+            case PH_UNMARK:
+                phase = (ctl->left && !(p.round_limit && ctl->round >= p.round_limit)) ? PH_KEYMIN : PH_DONE;
+                break;
             case PH_BFS_RESET: phase = PH_BFS_SEED; break;
             case PH_BFS_SEED:
                 lev = 1;
@@ -628,7 +740,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                     phase = PH_BFS_RESET;
                 } else if (job.ret == PH_LB_ALL && job.levels == h && bounded) {
                     // initial h-degrees done: now the initial (h-1)-degrees
-                    phase = start_job(p.list, ctl->nsrc, h - 1, p.dm, PH_LB_ALL);
+                    phase = start_job(ctl->nsrc, h - 1, p.dm, PH_LB_ALL, false);
                 } else {
                     phase = job.ret;
                     if (phase == PH_KEYMIN && !ctl->left) phase = PH_DONE;
@@ -681,7 +793,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     const size_t hq_len = (size_t)n + g->nnz / 256 + 1;
     const size_t ahq_len = (size_t)n + g->nnz / kAffChunk + 1;
     void *vis, *f0, *f1, *f2, *fnz, *hacc, *hdone, *counts, *bq, *bhq, *bctr, *alive, *dirty, *d, *dm, *lb,
-        *mark, *queue, *list, *kg, *ming, *ahq, *ctl, *sync;
+        *mark, *queue, *list, *kg, *ming, *ahq, *ctl, *sync, *seg;
     int rc;
     if ((rc = ws_get(ctx, WS_VIS, words * 8, &vis)) || (rc = ws_get(ctx, WS_FRT0, words * 8, &f0)) ||
         (rc = ws_get(ctx, WS_FRT1, words * 8, &f1)) || (rc = ws_get(ctx, WS_FRT2, words * 8, &f2)) ||
@@ -703,7 +815,8 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
         (rc = ws_get(ctx, WS_GRAPHK, (size_t)g->ngraphs * 8 + 8, &kg)) ||
         (rc = ws_get(ctx, WS_AHQ, (size_t)(h + 1) * ahq_len * 8, &ahq)) ||
         (rc = ws_get(ctx, WS_CTL, sizeof(PCtl), &ctl)) ||
-        (rc = ws_get(ctx, WS_SYNC, (size_t)(32 + 32 * kXcds) * 4, &sync)))
+        (rc = ws_get(ctx, WS_SYNC, (size_t)(32 + 32 * kXcds) * 4, &sync)) ||
+        (rc = ws_get(ctx, WS_SEG, (size_t)g->ngraphs * 8 + 64, &seg)))
         return rc;
     ming = (uint32_t *)kg + g->ngraphs;
     PParams p;
@@ -723,6 +836,9 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.h = h;
     p.bounded = bounded ? 1 : 0;
     p.profile = ctx->profile ? 1 : 0;
+    p.round_limit = ctx->round_limit;
+    p.progress = ctx->persist_progress_dev;
+    ctx->persist_progress[0] = ctx->persist_progress[1] = 0;
     p.alive = (uint8_t *)alive;
     p.dirty = (uint8_t *)dirty;
     p.d = (uint32_t *)d;
@@ -754,6 +870,10 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.bwork = (uint32_t *)(p.bqdeg + nq);
     p.bqcnt = p.bwork + nq;
     p.bhcnt = p.bqcnt + nq;
+    p.bnnz = (unsigned long long *)seg;
+    p.seg_cnt = (uint32_t *)((char *)seg + 8);
+    p.seg_pfx = p.seg_cnt + g->ngraphs;
+    p.vbase = g->vtx_base;
     uint32_t *sp = (uint32_t *)sync;
     p.sync.count = sp;
     p.sync.gen = sp + 16;
@@ -773,7 +893,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     hipStream_t st = ctx->stream;
 
     // one graph per argument set, replayed on later calls
-    khc_ctx::PersistGraph key{g, h, W, grid, bounded ? 1 : 0, p.profile, core, peel_round, nullptr};
+    khc_ctx::PersistGraph key{g, h, W, grid, bounded ? 1 : 0, p.profile, p.round_limit, core, peel_round, nullptr};
     hipGraphExec_t exec = nullptr;
     for (auto &e : ctx->persist_graphs)
         if (e.same_args(key)) exec = e.exec;
@@ -800,6 +920,15 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     }
     hipError_t e = hipGraphLaunch(exec, st);
     if (e != hipSuccess) return check_hip(ctx, e, "graph launch");
+    if (ctx->progress_fn) {
+        // report what the kernel publishes while it runs
+        auto last = std::chrono::steady_clock::now();
+        while ((e = hipStreamQuery(st)) == hipErrorNotReady) {
+            std::this_thread::sleep_for(std::chrono::milliseconds(5));
+            report_progress(ctx, &last, (uint32_t)ctx->persist_progress[0], ctx->persist_progress[1], 0u);
+        }
+        if (e != hipSuccess) return check_hip(ctx, e, "persistent decomposition");
+    }
     PCtl host_ctl;
     uint32_t host_sync[3];
     e = hipMemcpyAsync(&host_ctl, ctl, sizeof(PCtl), hipMemcpyDeviceToHost, st);

@@ -123,18 +123,24 @@ __device__ __forceinline__ void add_items(uint32_t x, uint64_t deg, int L, int h
     for (uint32_t c = 0; c < cnt; ++c) items[base + c] = make_uint2(x, c);
 }
 
-// Dirty live vertices whose lower bound reached the level.
-[[maybe_unused]] __global__ void collect_kernel(uint32_t n, const uint8_t *alive, const uint8_t *dirty, const uint32_t *lb,
-                               const uint32_t *part, uint32_t *list, uint32_t *s) {
+// Dirty live vertices whose lower bound reached the level while their stale
+// h-degree (an upper bound) is still above it: only for these is it open
+// whether they leave at this level.
+[[maybe_unused]] __global__ void collect_kernel(uint32_t n, const uint8_t *alive, const uint8_t *dirty,
+                                                const uint32_t *lb, const uint32_t *d, const uint32_t *part,
+                                                uint32_t *list, uint32_t *s) {
     const uint32_t k = block_level(part, s);
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool take = v < n && alive[v] && dirty[v] && lb[v] <= k;
+    const bool take = v < n && alive[v] && dirty[v] && lb[v] <= k && d[v] > k;
     const uint32_t at = wave_reserve(take, &s[R_RN]);
     if (take) list[at] = v;
 }
 
-// P = live (clean) vertices whose key <= k: core k, removal round r, queued
-// at level 0 with mark 1.
+// P = live vertices with d <= k: core k, removal round r, queued at level 0
+// with mark 1.  d is exact for clean vertices and an upper bound for dirty
+// ones, so a dirty vertex with d <= k leaves at this level without a
+// recompute; the dirty vertices left open were resolved by the cleaning
+// loop (their lower bound exceeds k).
 __global__ void select_kernel(uint32_t n, const uint64_t *row_ptr, const uint8_t *alive, const uint8_t *dirty,
                               const uint32_t *d, const uint32_t *part, uint32_t *mark, uint32_t *core,
                               uint32_t *round, uint32_t r, uint32_t *queue, uint32_t *s,
@@ -142,7 +148,8 @@ __global__ void select_kernel(uint32_t n, const uint64_t *row_ptr, const uint8_t
     const uint32_t k = block_level(part, s);
     if (blockIdx.x == 0 && threadIdx.x == 0) s[R_KNEW] = k;
     const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
-    const bool take = v < n && alive[v] && !(dirty && dirty[v]) && d[v] <= k;
+    (void)dirty;
+    const bool take = v < n && alive[v] && d[v] <= k;
     const uint32_t at = wave_reserve(take, &s[R_CNT]);
     if (take) {
         core[v] = k;

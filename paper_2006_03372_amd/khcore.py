@@ -31,6 +31,7 @@ OPT_PROFILE = 6
 OPT_DRIVER = 7
 OPT_PERSIST_WIDTH = 8
 OPT_BARRIER_TIMEOUT = 9
+OPT_ROUND_LIMIT = 10
 
 EXPORTED = [
     "khc_create", "khc_destroy", "khc_last_error", "khc_set_option", "khc_profile_read",
@@ -39,7 +40,7 @@ EXPORTED = [
     "khc_graph_create_batched", "khcore_decompose_batched",
     "khc_mlp_create", "khc_mlp_destroy", "khc_mlp_set_params", "khc_mlp_get_params",
     "khc_mlp_forward", "khc_mlp_gradient", "khc_mlp_train", "khc_features", "khcore_decompose_approx",
-    "khc_persist_profile_read", "khc_set_progress",
+    "khc_persist_profile_read", "khc_set_progress", "khc_autotune", "khc_mlp_save", "khc_mlp_load",
 ]
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32)
@@ -48,6 +49,22 @@ PERSIST_PHASES = ["init", "compact", "lb_all", "keymin", "level", "collect", "cl
                   "kill", "lbd", "unmark", "bfs_reset", "bfs_seed", "bfs_level", "bfs_scatter", "done"]
 
 N_PARAMS = 4801
+
+
+TUNE_MAX = 16
+
+
+class Tune(ctypes.Structure):
+    _fields_ = [("width_words", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
+                ("persistent", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
+                ("cand_width", ctypes.c_uint32 * TUNE_MAX), ("cand_waves", ctypes.c_uint32 * TUNE_MAX),
+                ("trial_ms", ctypes.c_double * TUNE_MAX)]
+
+    def as_dict(self):
+        k = self.candidates
+        return {"width_words": self.width_words, "waves_per_cu": self.waves_per_cu,
+                "persistent": bool(self.persistent),
+                "trials": [(self.cand_width[i], self.cand_waves[i], self.trial_ms[i]) for i in range(k)]}
 
 
 class KhcError(RuntimeError):
@@ -122,6 +139,9 @@ def load_library(path: str = LIB_PATH):
         "khcore_decompose_approx": ([P, P, u32, P, P, P, ctypes.POINTER(Stats)], i32),
         "khc_persist_profile_read": ([P, P, P, i32], i32),
         "khc_set_progress": ([P, PROGRESS_FN, P, u32], i32),
+        "khc_autotune": ([P, P, u32, u32, ctypes.POINTER(Tune)], i32),
+        "khc_mlp_save": ([P, P, ctypes.c_char_p], i32),
+        "khc_mlp_load": ([P, P, ctypes.c_char_p], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -181,6 +201,13 @@ class Context:
             return
         self._progress = PROGRESS_FN(lambda _u, r, removed, level: fn(int(r), int(removed), int(level)))
         self._check(self.lib.khc_set_progress(self.handle, self._progress, None, interval_ms))
+
+    def autotune(self, graph: "Graph", h: int, rounds: int = 64) -> dict:
+        """Time trial decompositions (cut after `rounds` rounds) over the
+        width x waves-per-CU candidates and keep the fastest on this context."""
+        t = Tune()
+        self._check(self.lib.khc_autotune(self.handle, graph.handle, h, rounds, ctypes.byref(t)))
+        return t.as_dict()
 
     def persist_profile_read(self, reset: bool = True) -> dict:
         """Per-phase time (ms) and counts of the persistent driver's runs made
@@ -379,6 +406,12 @@ class Mlp:
                                                          p.ctypes.data_as(ctypes.c_void_p),
                                                          g.ctypes.data_as(ctypes.c_void_p)))
         return p, g
+
+    def save(self, path: str):
+        self.ctx._check(self.ctx.lib.khc_mlp_save(self.ctx.handle, self.handle, os.fsencode(path)))
+
+    def load(self, path: str):
+        self.ctx._check(self.ctx.lib.khc_mlp_load(self.ctx.handle, self.handle, os.fsencode(path)))
 
     def set(self, params):
         p = np.ascontiguousarray(params, dtype=np.float32)

@@ -150,3 +150,20 @@ def test_progress_reports(ctx):
     assert [x[0] for x in seen] == list(range(1, st["rounds"] + 1))
     assert seen[-1][1] == g.n and seen[-1][2] == c.max()
     assert all(a[1] < b[1] and a[2] <= b[2] for a, b in zip(seen, seen[1:]))
+
+
+def test_persistent_progress_reports(ctx):
+    """The persistent kernel publishes its progress to host memory while it
+    runs; reports are monotone and never ahead of the final statistics."""
+    g = synth.rmat(12, 8, seed=1)
+    seen = []
+    ctx.set_progress(lambda r, removed, level: seen.append((r, removed)), 0)
+    try:
+        c, r, st = _gpu_core(ctx, g, 3, 1, 16, 1)
+    finally:
+        ctx.set_progress(None)
+    print("reports", len(seen), "wall ms", st["wall_ms"], flush=True)
+    if st["wall_ms"] > 100:
+        assert seen
+    assert all(a[0] <= b[0] and a[1] <= b[1] for a, b in zip(seen, seen[1:]))
+    assert all(x[0] <= st["rounds"] and x[1] <= g.n for x in seen)

@@ -189,3 +189,30 @@ def test_approx_without_network_is_valid(ctx):
     c = core.cpu().numpy().view(np.uint32)
     assert (c <= ub.cpu().numpy().view(np.uint32)).all()
     assert st["rounds"] >= 1
+
+
+def test_save_and_load(ctx, tmp_path):
+    import torch
+    from paper_2006_03372_amd import khcore
+    a = ctx.mlp(seed=5)
+    a.set(_rand_params(3))
+    path = str(tmp_path / "net.bin")
+    a.save(path)
+    b = ctx.mlp(seed=6)
+    b.load(path)
+    pa, _ = a.get()
+    pb, _ = b.get()
+    assert np.array_equal(pa.view(np.uint32), pb.view(np.uint32))
+    X = torch.from_numpy(np.random.default_rng(2).uniform(0, 1.6, size=(300, 8)).astype(np.float32)).cuda()
+    assert torch.equal(a.forward(X), b.forward(X))
+    # a truncated file is refused and leaves the network as it was
+    with open(path, "rb") as f:
+        blob = f.read()
+    with open(path, "wb") as f:
+        f.write(blob[:-4])
+    with pytest.raises(khcore.KhcError):
+        b.load(path)
+    pb2, _ = b.get()
+    assert np.array_equal(pb.view(np.uint32), pb2.view(np.uint32))
+    a.close()
+    b.close()
