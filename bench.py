@@ -6,6 +6,10 @@ throughput is in GTEPS: traversed edges, where the work of one vertex is the
 number of arcs a scalar bounded BFS from it examines (khdeg_scanned_arcs),
 divided by the step time, 10^9 per second.
 
+After the timed steps, the exact (k,h)-core decomposition is timed once on
+R-MAT scale 16 (edge factor 8) at h = 3 (--decompose-scale 20 times the
+R-MAT-20 graph instead, which takes minutes).
+
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
 """
 import argparse
@@ -40,10 +44,45 @@ def profiled_traffic(path=os.path.join(ROOT, "profiles", "level_kernel_rmat20_h3
         for key in ("traffic_bytes_per_launch:", "source_sha256:"):
             if line.startswith(key):
                 vals[key] = line.split(":", 1)[1].strip()
-    src = os.path.join(ROOT, "paper_2006_03372_amd", "csrc", "khc_bfs.hip")
-    if vals.get("source_sha256:") != hashlib.sha256(open(src, "rb").read()).hexdigest():
+    if vals.get("source_sha256:") != level_source_hash():
         return None
     return float(vals["traffic_bytes_per_launch:"])
+
+
+def level_source_hash():
+    """sha256 over the sources the BFS level kernel is built from."""
+    import hashlib
+    h = hashlib.sha256()
+    for name in ("khc_bfs.hip", "khc_level.h", "khc_internal.h"):
+        with open(os.path.join(ROOT, "paper_2006_03372_amd", "csrc", name), "rb") as f:
+            h.update(f.read())
+    return h.hexdigest()
+
+
+def decomposition(ctx, scale, edge_factor, h, log):
+    """One exact decomposition, host-driven rounds (wall time, statistics)."""
+    import torch
+    from paper_2006_03372_amd import khcore, synth
+    g = synth.rmat(scale, edge_factor, seed=1)
+    gr = ctx.graph(g)
+    ctx.set_option(khcore.OPT_DRIVER, 0)
+    ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
+    ctx.set_option(khcore.OPT_WAVES_PER_CU, 8)
+    t0 = time.perf_counter()
+    ctx.set_progress(lambda r, removed, level: log(f"  decomposition {time.perf_counter() - t0:.0f} s: "
+                                                   f"round {r}, {removed} removed, level {level}"), 20000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    core, _, st = ctx.core(gr, h)
+    torch.cuda.synchronize()
+    wall = time.perf_counter() - t0
+    ctx.set_progress(None)
+    gr.close()
+    return {"workload": f"khcore_decompose, R-MAT scale {scale} (ef {edge_factor}, seed 1), h={h}, "
+                        "bounded schedule, host-driven rounds, W=32, 8 waves/CU",
+            "n": g.n, "edges": g.num_edges, "wall_s": round(wall, 3), "rounds": st["rounds"],
+            "h_recomputes": st["h_recomputes"], "hm1_recomputes": st["hm1_recomputes"],
+            "max_core": int(core.max().item())}
 
 
 def cpu_baseline(g, h, budget_s=15.0, seed=0):
@@ -80,6 +119,8 @@ def main():
     ap.add_argument("--h", type=int, default=3)
     ap.add_argument("--width", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--decompose-scale", type=int, default=16,
+                    help="R-MAT scale of the timed decomposition (0: skip; 20 takes minutes)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="one untimed-warmup-free step without the work count or CPU leg, for profilers")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -104,7 +145,7 @@ def main():
         print(json.dumps({"calibration_copy_bytes": nbytes, "copies": 3}))
         return
     if args.profile_pass:
-        args.warmup, args.steps, args.no_cpu = 0, 1, True
+        args.warmup, args.steps, args.no_cpu, args.decompose_scale = 0, 1, True, 0
 
     t = time.time()
     g = synth.rmat(args.scale, args.edge_factor, seed=1)
@@ -173,6 +214,10 @@ def main():
         log("timing the CPU oracle on a sample ...")
         result["cpu_baseline"] = cpu_baseline(g, h)
     gr.close()
+    if args.decompose_scale:
+        ef = 16 if args.decompose_scale >= 20 else 8
+        log(f"timing the decomposition of R-MAT scale {args.decompose_scale} at h={h} ...")
+        result["decomposition"] = decomposition(ctx, args.decompose_scale, ef, h, log)
     ctx.close()
     print(json.dumps(result), flush=True)
 

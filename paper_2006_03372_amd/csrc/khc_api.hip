@@ -239,7 +239,7 @@ int upload(khc_ctx *ctx, const std::vector<T> &v, T **out) {
 
 }  // namespace
 
-int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out);
+int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out, const std::vector<uint64_t> *vbase);
 
 }  // namespace khc
 
@@ -408,7 +408,7 @@ int khc_graph_create(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
     *out = nullptr;
     if (ctx->sticky) return set_error(ctx, KHC_EHIP, "context has a sticky HIP error");
     (void)hipSetDevice(ctx->device);
-    return graph_create_impl(ctx, g, out);
+    return graph_create_impl(ctx, g, out, nullptr);
 }
 
 }  // extern "C"
@@ -513,7 +513,7 @@ int khc_graph_create_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base,
     }
     khc_csr u{n, nnz, row_ptr, ucol};
     khc_graph *gr = nullptr;
-    if ((rc = graph_create_impl(ctx, &u, &gr))) {
+    if ((rc = graph_create_impl(ctx, &u, &gr, &vb))) {
         cleanup();
         return rc;
     }
@@ -549,13 +549,15 @@ void report_progress(khc_ctx *ctx, std::chrono::steady_clock::time_point *last, 
     ctx->progress_fn(ctx->progress_user, rounds, removed, level);
 }
 
-int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
+int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out, const std::vector<uint64_t> *vbase) {
     int rc = check_csr_args(ctx, g);
     if (rc) return rc;
     if (ctx->validate && (rc = validate_impl(ctx, g))) return rc;
 
-    // Row schedule: degrees from the offsets, light rows bucketed by degree
-    // (descending), heavy rows sorted by degree and cut into chunks.
+    // Row schedule: light rows (<= kHeavyRowArcs arcs) by descending degree,
+    // heavy rows by descending degree and cut into chunks.  Several graphs
+    // packed together (vbase) are scheduled graph by graph, so the rows of
+    // consecutive graphs form one range of each list.
     const uint32_t n = g->n;
     std::vector<uint64_t> rp(n + 1);
     hipError_t e = hipMemcpyAsync(rp.data(), g->row_ptr, (n + 1) * sizeof(uint64_t),
@@ -563,34 +565,43 @@ int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
     if (e == hipSuccess) e = hipStreamSynchronize(ctx->stream);
     if (e != hipSuccess) return check_hip(ctx, e, "row_ptr download");
     if (rp[n] != g->nnz) return set_error(ctx, KHC_EGRAPH, "row_ptr[n] != nnz");
-    std::vector<uint32_t> bucket(kHeavyRowArcs + 2, 0);
-    std::vector<uint32_t> heavy;
+    const uint32_t G = vbase ? (uint32_t)(vbase->size() - 1) : 1u;
+    auto deg = [&](uint32_t v) { return rp[v + 1] - rp[v]; };
+    std::vector<uint32_t> light, heavy, chunk_heavy, chunk_first, light_first(G + 1, 0), gchunk_first(G + 1, 0);
+    light.reserve(n);
     uint32_t maxdeg = 0;
-    for (uint32_t v = 0; v < n; ++v) {
-        uint64_t d = rp[v + 1] - rp[v];
-        if (d > maxdeg) maxdeg = (uint32_t)std::min<uint64_t>(d, 0xFFFFFFFFu);
-        if (d > kHeavyRowArcs) heavy.push_back(v);
-        else bucket[kHeavyRowArcs - d]++;  // descending degree order
+    std::vector<uint32_t> bucket(kHeavyRowArcs + 2), start(kHeavyRowArcs + 2);
+    for (uint32_t gi = 0; gi < G; ++gi) {
+        const uint32_t v0 = vbase ? (uint32_t)(*vbase)[gi] : 0u, v1 = vbase ? (uint32_t)(*vbase)[gi + 1] : n;
+        light_first[gi] = (uint32_t)light.size();
+        gchunk_first[gi] = (uint32_t)chunk_heavy.size();
+        std::fill(bucket.begin(), bucket.end(), 0u);
+        const size_t heavy0 = heavy.size();
+        for (uint32_t v = v0; v < v1; ++v) {
+            const uint64_t d = deg(v);
+            if (d > maxdeg) maxdeg = (uint32_t)std::min<uint64_t>(d, 0xFFFFFFFFu);
+            if (d > kHeavyRowArcs) heavy.push_back(v);
+            else bucket[kHeavyRowArcs - d]++;  // descending degree order
+        }
+        start[0] = (uint32_t)light.size();
+        for (uint32_t i = 1; i < start.size(); ++i) start[i] = start[i - 1] + bucket[i - 1];
+        light.resize(light.size() + (v1 - v0) - (heavy.size() - heavy0));
+        for (uint32_t v = v0; v < v1; ++v) {
+            const uint64_t d = deg(v);
+            if (d <= kHeavyRowArcs) light[start[kHeavyRowArcs - d]++] = v;
+        }
+        std::sort(heavy.begin() + heavy0, heavy.end(), [&](uint32_t a, uint32_t b) {
+            return deg(a) != deg(b) ? deg(a) > deg(b) : a < b;
+        });
+        for (size_t i = heavy0; i < heavy.size(); ++i) {
+            const uint32_t nch = (uint32_t)((deg(heavy[i]) + kChunkArcs - 1) / kChunkArcs);
+            chunk_first.push_back((uint32_t)chunk_heavy.size());
+            for (uint32_t c = 0; c < nch; ++c) chunk_heavy.push_back((uint32_t)i);
+        }
     }
-    std::vector<uint32_t> start(kHeavyRowArcs + 2, 0);
-    for (uint32_t i = 1; i < start.size(); ++i) start[i] = start[i - 1] + bucket[i - 1];
-    std::vector<uint32_t> light(n - heavy.size());
-    for (uint32_t v = 0; v < n; ++v) {
-        uint64_t d = rp[v + 1] - rp[v];
-        if (d <= kHeavyRowArcs) light[start[kHeavyRowArcs - d]++] = v;
-    }
-    std::sort(heavy.begin(), heavy.end(), [&](uint32_t a, uint32_t b) {
-        uint64_t da = rp[a + 1] - rp[a], db = rp[b + 1] - rp[b];
-        return da != db ? da > db : a < b;
-    });
-    std::vector<uint32_t> chunk_heavy, chunk_first(heavy.size() + 1, 0);
-    for (uint32_t i = 0; i < heavy.size(); ++i) {
-        uint64_t d = rp[heavy[i] + 1] - rp[heavy[i]];
-        uint32_t nch = (uint32_t)((d + kChunkArcs - 1) / kChunkArcs);
-        chunk_first[i] = (uint32_t)chunk_heavy.size();
-        for (uint32_t c = 0; c < nch; ++c) chunk_heavy.push_back(i);
-    }
-    chunk_first[heavy.size()] = (uint32_t)chunk_heavy.size();
+    light_first[G] = (uint32_t)light.size();
+    gchunk_first[G] = (uint32_t)chunk_heavy.size();
+    chunk_first.push_back((uint32_t)chunk_heavy.size());
 
     khc_graph *gr = new khc_graph();
     gr->ctx = ctx;
@@ -599,17 +610,25 @@ int graph_create_impl(khc_ctx *ctx, const khc_csr *g, khc_graph **out) {
     gr->row_ptr = g->row_ptr;
     gr->col = g->col;
     gr->n_light = (uint32_t)light.size();
-    for (uint32_t v : light) {
-        const uint64_t d = rp[v + 1] - rp[v];
-        gr->n_light_mid += d > kMidDeg;
-        gr->n_light_nz += d > 0;
+    if (!vbase) {
+        for (uint32_t v : light) {
+            const uint64_t d = rp[v + 1] - rp[v];
+            gr->n_light_mid += d > kMidDeg;
+            gr->n_light_nz += d > 0;
+        }
+    } else {
+        // not one descending-degree order: every light row on the one-lane path
+        gr->n_light_mid = 0;
+        gr->n_light_nz = gr->n_light;
     }
     gr->n_heavy = (uint32_t)heavy.size();
     gr->n_chunks = (uint32_t)chunk_heavy.size();
     gr->max_degree = maxdeg;
     if ((rc = upload(ctx, light, &gr->light_rows)) || (rc = upload(ctx, heavy, &gr->heavy_rows)) ||
         (rc = upload(ctx, chunk_heavy, &gr->chunk_heavy)) ||
-        (rc = upload(ctx, chunk_first, &gr->chunk_first))) {
+        (rc = upload(ctx, chunk_first, &gr->chunk_first)) ||
+        (vbase && ((rc = upload(ctx, light_first, &gr->light_first)) ||
+                   (rc = upload(ctx, gchunk_first, &gr->graph_chunk_first))))) {
         khc_graph_destroy(gr);
         return rc;
     }
@@ -634,6 +653,8 @@ int khc_graph_destroy(khc_graph *g) {
     if (g->heavy_rows) (void)hipFree(g->heavy_rows);
     if (g->chunk_heavy) (void)hipFree(g->chunk_heavy);
     if (g->chunk_first) (void)hipFree(g->chunk_first);
+    if (g->light_first) (void)hipFree(g->light_first);
+    if (g->graph_chunk_first) (void)hipFree(g->graph_chunk_first);
     delete g;
     return KHC_OK;
 }

@@ -326,8 +326,11 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
             p.counts = (uint32_t *)counts;
             p.nnz = g->nnz;
             p.n = n;
-            p.n_light = g->n_light;
-            p.n_chunks = g->n_chunks;
+            p.light_lo = 0;
+            p.light_hi = g->n_light;
+            p.chunk_lo = 0;
+            p.chunk_hi = g->n_chunks;
+            p.count_keep = 0;
             p.gid = nullptr;  // one graph, or batched graphs with every lane of every row read
             p.seg_pfx = nullptr;
             p.batch_base = 0;

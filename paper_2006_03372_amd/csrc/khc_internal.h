@@ -125,6 +125,10 @@ struct khc_graph {
     uint32_t *chunk_first = nullptr;  // first chunk of each heavy row [n_heavy + 1]
     uint32_t n_chunks = 0;
     uint32_t max_degree = 0;
+    // graphs packed together: light rows and chunks of graph g start at
+    // light_first[g] and graph_chunk_first[g] (device, [ngraphs + 1])
+    uint32_t *light_first = nullptr;
+    uint32_t *graph_chunk_first = nullptr;
     // several graphs packed as one disjoint union: gid[v] = graph of v
     uint32_t ngraphs = 1;
     uint32_t *gid = nullptr;       // device, owned (null: one graph)

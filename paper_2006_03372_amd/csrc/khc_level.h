@@ -68,7 +68,8 @@ constexpr int kUnroll = 8;            // independent gathers in flight per lane
 constexpr int kPushFactor = 16;       // push when frontier arcs * factor < all arcs
 constexpr int kGrab = 4;              // push work grab: one frontier item per wavefront
 constexpr uint32_t kPushChunk = 256;  // arcs per push item of a heavy frontier row
-constexpr int kStage = 1024;          // LDS staging of frontier rows (pull levels)
+constexpr int kStage = 4096;          // LDS staging of frontier rows
+constexpr int kStageItem = 1024;      // most rows one work item can stage
 
 // Frontier list of one level: every row once (q, count, total degree) and,
 // for rows with more than kPushChunk arcs, one push item per kPushChunk arcs
@@ -107,10 +108,18 @@ struct LevelParams {
     uint32_t *hdone;
     uint32_t *work;    // work-item counter of this level
     uint32_t *counts;  // per-lane reached-vertex totals, summed over levels
+    // One persistent kernel: the workgroup's LDS totals carry over between
+    // the levels of a batch (cleared at its first level) and are added to
+    // counts once, at the last level, instead of after every level.
+    int count_keep;
+    int count_first;
     uint64_t nnz;  // arcs the pull direction would read (push/pull choice)
     uint32_t n;
-    uint32_t n_light;
-    uint32_t n_chunks;
+    // pull visits light rows light_rows[light_lo, light_hi) and heavy-row
+    // chunks [chunk_lo, chunk_hi) (all of them for one graph; the batch's
+    // graphs for graphs packed together)
+    uint32_t light_lo, light_hi;
+    uint32_t chunk_lo, chunk_hi;
     // Graph windows (batched graphs; null for one graph): the batch's
     // sources are grouped by graph, graph g owning source slots
     // [seg_pfx[g], seg_pfx[g+1]) of the job and this batch the slots
@@ -192,27 +201,6 @@ static __device__ __forceinline__ void add_push_items(const Frontier &f, uint32_
     for (uint32_t c = 0; c < nch; ++c) f.hq[at + c] = (uint64_t)y | ((uint64_t)c << 32);
 }
 
-// Wave-aggregated append straight to the global frontier list.  Must be
-// reached by every lane of the wavefront.
-static __device__ __forceinline__ void append_direct(bool take, uint32_t y, uint64_t dy, const Frontier &f) {
-    const uint64_t m = __ballot(take);
-    if (!m) return;
-    const int lane = threadIdx.x & 63;
-    const int leader = __builtin_ctzll(m);
-    uint64_t dsum = take ? dy : 0;
-    for (int off = 32; off > 0; off >>= 1) dsum += __shfl_xor(dsum, off, 64);
-    uint32_t base = 0;
-    if (lane == leader) {
-        base = atomicAdd(f.qcnt, (uint32_t)__builtin_popcountll(m));
-        atomicAdd(f.qdeg, (unsigned long long)dsum);
-    }
-    base = __shfl(base, leader, 64);
-    if (take) {
-        f.q[base + __builtin_popcountll(m & ((1ull << lane) - 1ull))] = y;
-        add_push_items(f, y, dy);
-    }
-}
-
 // Wave-aggregated append to the workgroup's LDS staging list.
 static __device__ __forceinline__ void append_staged(bool take, uint32_t y, uint32_t *s_stage,
                                               uint32_t *s_sn) {
@@ -262,7 +250,7 @@ static __device__ void flush_staged(const Frontier &f, const uint64_t *row_ptr, 
 // on this level's frontier.  One wavefront, lanes over (arc, word) pairs.
 template <int W, bool LAST>
 __device__ void push_range(const LevelParams &p, uint32_t x, uint64_t ab, uint64_t ae,
-                           uint32_t *s_counts) {
+                           uint32_t *s_counts, uint32_t *s_stage, uint32_t *s_sn) {
     const int lane = threadIdx.x & 63;
     const uint64_t myw = lane < W ? p.frt_in[(size_t)x * W + lane] : 0ull;
     const uint64_t nzmask = __ballot(myw != 0);
@@ -272,7 +260,6 @@ __device__ void push_range(const LevelParams &p, uint32_t x, uint64_t ab, uint64
         const uint64_t pr = base + lane;
         bool take = false;
         uint32_t y = 0;
-        uint64_t dy = 0;
         if (pr < pairs) {
             const uint64_t arc = pr / nz;
             uint32_t k = (uint32_t)(pr - arc * nz);
@@ -292,16 +279,15 @@ __device__ void push_range(const LevelParams &p, uint32_t x, uint64_t ab, uint64
                         if constexpr (!LAST)
                             atomicOr((unsigned long long *)(p.frt_out + (size_t)y * W + w),
                                      (unsigned long long)tn);
+                        // listed even at the counting level: its vis words
+                        // changed, and the batch clears exactly the listed rows
                         const uint32_t ybit = 1u << (y & 31);
-                        if (!(atomicOr(&p.fnz_out[y >> 5], ybit) & ybit)) {
-                            take = true;
-                            dy = p.row_ptr[y + 1] - p.row_ptr[y];
-                        }
+                        take = !(atomicOr(&p.fnz_out[y >> 5], ybit) & ybit);
                     }
                 }
             }
         }
-        append_direct(take, y, dy, p.out);
+        append_staged(take, y, s_stage, s_sn);
     }
 }
 
@@ -353,7 +339,8 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
         for (size_t i = gtid; i < nclr; i += gstride) p.fnz_clr[p.q_clr[i] >> 5] = 0;
     }
 
-    for (int i = tid; i < 64 * W; i += kBlockThreads) s_counts[i] = 0;
+    if (!p.count_keep || p.count_first)
+        for (int i = tid; i < 64 * W; i += kBlockThreads) s_counts[i] = 0;
     if (tid == 0) s_sn = 0;
     uint64_t pl[WPL][kPlanes];
 #pragma unroll
@@ -366,13 +353,16 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
     const uint32_t qn_in = *p.qcnt_in;
     const uint32_t hn_in = *p.hcnt_in;
     const uint32_t light_grabs = (qn_in + kGrab - 1) / kGrab;
+    const uint32_t n_chunk_items = p.chunk_hi - p.chunk_lo;
+    const uint32_t n_light_rows = p.light_hi - p.light_lo;
     const uint32_t n_items = push ? light_grabs + (hn_in + kGrab - 1) / kGrab
-                                  : p.n_chunks + (p.n_light + GROUPS * PASSES - 1) / (GROUPS * PASSES);
+                                  : n_chunk_items + (n_light_rows + GROUPS * PASSES - 1) / (GROUPS * PASSES);
     __syncthreads();
 
     // The first item of each workgroup is its block index; later items come
-    // from the counter (offset by the grid size), so workgroups without
-    // work leave without touching it.
+    // from the counter (offset by the grid size), so workgroups without work
+    // leave without touching it.  One item per take: taking several per
+    // atomic balanced the levels worse than the atomics it saved.
     for (bool first = true;; first = false) {
         if (tid == 0) s_item = first ? blockIdx.x : gridDim.x + atomicAdd(p.work, 1u);
         __syncthreads();
@@ -386,7 +376,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                 if (qi < qn_in) {
                     const uint32_t x = p.q_in[qi];
                     const uint64_t rb = p.row_ptr[x], re = p.row_ptr[x + 1];
-                    if (re - rb <= kPushChunk) push_range<W, LAST>(p, x, rb, re, s_counts);
+                    if (re - rb <= kPushChunk) push_range<W, LAST>(p, x, rb, re, s_counts, s_stage, &s_sn);
                 }
             } else {
                 const uint32_t hi = (item - light_grabs) * kGrab + wave;
@@ -396,12 +386,13 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                     const uint64_t rb = p.row_ptr[x], re = p.row_ptr[x + 1];
                     const uint64_t ab = rb + (it >> 32) * kPushChunk;
                     const uint64_t ae = ab + kPushChunk < re ? ab + kPushChunk : re;
-                    push_range<W, LAST>(p, x, ab, ae, s_counts);
+                    push_range<W, LAST>(p, x, ab, ae, s_counts, s_stage, &s_sn);
                 }
             }
-        } else if (item < p.n_chunks) {
+        } else if (item < n_chunk_items) {
             // ---- pull, one chunk of a heavy row, whole workgroup ----
-            const uint32_t hi = p.chunk_heavy[item];
+            const uint32_t chunk = p.chunk_lo + item;
+            const uint32_t hi = p.chunk_heavy[chunk];
             const uint32_t y = p.heavy_rows[hi];
             int w0 = 0, w1 = W - 1;
             const bool live = (!p.alive || p.alive[y]) && row_window<W>(p, y, &w0, &w1);
@@ -411,7 +402,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                 const uint32_t c0 = p.chunk_first[hi];
                 const uint32_t nch = p.chunk_first[hi + 1] - c0;
                 const uint64_t rb = p.row_ptr[y], re = p.row_ptr[y + 1];
-                const uint64_t b = rb + (uint64_t)(item - c0) * kChunkArcs;
+                const uint64_t b = rb + (uint64_t)(chunk - c0) * kChunkArcs;
                 const uint64_t e = (b + kChunkArcs < re) ? b + kChunkArcs : re;
                 uint64_t acc[WPL];
 #pragma unroll
@@ -488,11 +479,11 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
             }
         } else {
             // ---- pull, light rows: one lane group per row ----
-            const uint32_t tile = item - p.n_chunks;
+            const uint32_t tile = item - n_chunk_items;
             for (int pass = 0; pass < PASSES; ++pass) {
                 const uint32_t idx = (tile * PASSES + pass) * GROUPS + group;
-                bool valid = idx < p.n_light;
-                const uint32_t y = valid ? p.light_rows[idx] : 0u;
+                bool valid = idx < n_light_rows;
+                const uint32_t y = valid ? p.light_rows[p.light_lo + idx] : 0u;
                 if (valid && p.alive && !p.alive[y]) valid = false;
                 int w0 = 0, w1 = W - 1;
                 if (valid && !row_window<W>(p, y, &w0, &w1)) valid = false;
@@ -560,17 +551,16 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
             }
         }
         __syncthreads();
-        if constexpr (!LAST) {
-            // at most 256 rows are staged per work item
-            if (s_sn > kStage - 256) flush_staged(p.out, p.row_ptr, s_stage, &s_sn, &s_base, &s_deg);
-        }
+        // (the counting level stages rows only when it pushes: their vis changed)
+        if (s_sn > kStage - kStageItem) flush_staged(p.out, p.row_ptr, s_stage, &s_sn, &s_base, &s_deg);
     }
 
-    if constexpr (!LAST) flush_staged(p.out, p.row_ptr, s_stage, &s_sn, &s_base, &s_deg);
+    flush_staged(p.out, p.row_ptr, s_stage, &s_sn, &s_base, &s_deg);
     planes_flush<WPL>(pl, s_counts, lig * WPL);
     __syncthreads();
-    for (int i = tid; i < 64 * W; i += kBlockThreads)
-        if (s_counts[i]) atomicAdd(&p.counts[i], s_counts[i]);
+    if (!p.count_keep || LAST)
+        for (int i = tid; i < 64 * W; i += kBlockThreads)
+            if (s_counts[i]) atomicAdd(&p.counts[i], s_counts[i]);
     __syncthreads();
 }
 

@@ -74,6 +74,13 @@ struct Sync {
     uint64_t timeout_ticks;
 };
 
+// The graphs a BFS batch covers: their arcs (push/pull choice) and their
+// ranges of the light-row and heavy-chunk schedules.
+struct BatchRange {
+    unsigned long long arcs;
+    uint32_t light_lo, light_hi, chunk_lo, chunk_hi;
+};
+
 struct PParams {
     const uint64_t *row_ptr;
     const uint32_t *col;
@@ -113,7 +120,8 @@ struct PParams {
     // prefix over graphs, computed when a job starts.
     uint32_t *seg_cnt, *seg_pfx;
     const uint64_t *vbase;      // graph offsets [ngraphs + 1] (null: one graph)
-    unsigned long long *bnnz;   // arcs of the graphs the current batch covers
+    const uint32_t *light_first, *gchunk_first;  // schedule ranges per graph (null: one graph)
+    BatchRange *brange;         // what the current batch covers
     Sync sync;
 };
 
@@ -586,14 +594,18 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 f0.hq = p.bhq;
                 f0.hcnt = p.bhcnt;
                 if (gtid() == 0) {
-                    // arcs of the graphs this batch covers (sources are grouped by graph)
-                    unsigned long long arcs = p.nnz;
+                    // the graphs this batch covers (sources are grouped by graph)
+                    BatchRange br{p.nnz, 0u, p.n_light, 0u, p.n_chunks};
                     if (p.vbase) {
                         const uint32_t ga = graph_of(p, job_source(p, first));
                         const uint32_t gb = graph_of(p, job_source(p, first + cnt - 1));
-                        arcs = p.row_ptr[p.vbase[gb + 1]] - p.row_ptr[p.vbase[ga]];
+                        br.arcs = p.row_ptr[p.vbase[gb + 1]] - p.row_ptr[p.vbase[ga]];
+                        br.light_lo = p.light_first[ga];
+                        br.light_hi = p.light_first[gb + 1];
+                        br.chunk_lo = p.gchunk_first[ga];
+                        br.chunk_hi = p.gchunk_first[gb + 1];
                     }
-                    *p.bnnz = arcs;
+                    *p.brange = br;
                 }
                 for (size_t l = gtid(); l < cnt; l += gstride()) {
                     const uint32_t s = job_source(p, first + (uint32_t)l);
@@ -641,10 +653,15 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 lp.hdone = p.hdone;
                 lp.work = p.bwork + lev;
                 lp.counts = p.counts;
-                lp.nnz = *p.bnnz;
+                lp.count_keep = 1;
+                lp.count_first = lev == 1;
+                const BatchRange br = *p.brange;
+                lp.nnz = br.arcs;
                 lp.n = n;
-                lp.n_light = p.n_light;
-                lp.n_chunks = p.n_chunks;
+                lp.light_lo = br.light_lo;
+                lp.light_hi = br.light_hi;
+                lp.chunk_lo = br.chunk_lo;
+                lp.chunk_hi = br.chunk_hi;
                 lp.gid = p.gid;
                 lp.seg_pfx = p.gid ? p.seg_pfx : nullptr;
                 lp.batch_base = batch * per;
@@ -816,7 +833,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
         (rc = ws_get(ctx, WS_AHQ, (size_t)(h + 1) * ahq_len * 8, &ahq)) ||
         (rc = ws_get(ctx, WS_CTL, sizeof(PCtl), &ctl)) ||
         (rc = ws_get(ctx, WS_SYNC, (size_t)(32 + 32 * kXcds) * 4, &sync)) ||
-        (rc = ws_get(ctx, WS_SEG, (size_t)g->ngraphs * 8 + 64, &seg)))
+        (rc = ws_get(ctx, WS_SEG, (size_t)g->ngraphs * 8 + 64 + 32, &seg)))
         return rc;
     ming = (uint32_t *)kg + g->ngraphs;
     PParams p;
@@ -870,10 +887,12 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.bwork = (uint32_t *)(p.bqdeg + nq);
     p.bqcnt = p.bwork + nq;
     p.bhcnt = p.bqcnt + nq;
-    p.bnnz = (unsigned long long *)seg;
-    p.seg_cnt = (uint32_t *)((char *)seg + 8);
+    p.brange = (BatchRange *)seg;
+    p.seg_cnt = (uint32_t *)((char *)seg + 32);
     p.seg_pfx = p.seg_cnt + g->ngraphs;
     p.vbase = g->vtx_base;
+    p.light_first = g->light_first;
+    p.gchunk_first = g->graph_chunk_first;
     uint32_t *sp = (uint32_t *)sync;
     p.sync.count = sp;
     p.sync.gen = sp + 16;
