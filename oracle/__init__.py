@@ -14,6 +14,10 @@ Two implementations:
                  level-synchronous peel with from-scratch recomputation and
                  per-round trace, the peeling-order certificate), loaded
                  here through ctypes.
+The MLP of the learned approximate mode has its own reference in mlp.py
+(pinned to finite differences).  The approximate decomposition itself has
+no oracle: its output is an estimate whose error the tests measure against
+the exact core numbers computed here (parity unpinned by design).
 """
 from __future__ import annotations
 
