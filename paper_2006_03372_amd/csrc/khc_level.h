@@ -361,8 +361,10 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
 
     // The first item of each workgroup is its block index; later items come
     // from the counter (offset by the grid size), so workgroups without work
-    // leave without touching it.  One item per take: taking several per
-    // atomic balanced the levels worse than the atomics it saved.
+    // leave without touching it.  Measured against the alternatives (several
+    // items per atomic; three quarters of the items dealt round-robin first)
+    // taking one item per atomic balanced the big levels best: they lost
+    // 7-32% (up to 20% of the R-MAT-20 level rate).
     for (bool first = true;; first = false) {
         if (tid == 0) s_item = first ? blockIdx.x : gridDim.x + atomicAdd(p.work, 1u);
         __syncthreads();
@@ -487,12 +489,40 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                 if (valid && p.alive && !p.alive[y]) valid = false;
                 int w0 = 0, w1 = W - 1;
                 if (valid && !row_window<W>(p, y, &w0, &w1)) valid = false;
+                // Narrow window (batched graphs: the row's lanes fit in one
+                // lane's words): the group's lanes split the arcs instead of
+                // the words, and OR their gathers into the owning lane.
+                const bool narrow = LPR > 1 && valid && p.gid != nullptr && w0 / WPL == w1 / WPL;
+                const int own = w0 / WPL;
                 // this lane's words meet the row's window
-                const bool lane_on = valid && lig * WPL + WPL - 1 >= w0 && lig * WPL <= w1;
+                const bool lane_on =
+                    valid && (narrow ? lig == own : (lig * WPL + WPL - 1 >= w0 && lig * WPL <= w1));
                 uint64_t acc[WPL];
 #pragma unroll
                 for (int j = 0; j < WPL; ++j) acc[j] = 0;
-                if (lane_on) {
+                if (narrow) {
+                    const uint64_t rb = p.row_ptr[y], re = p.row_ptr[y + 1];
+                    uint64_t a = rb + lig;
+                    for (; a + (uint64_t)(kUnroll - 1) * LPR < re; a += (uint64_t)kUnroll * LPR) {
+                        uint32_t xs[kUnroll];
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u) xs[u] = p.col[a + (uint64_t)u * LPR];
+                        uint64_t t[kUnroll][WPL];
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u)
+                            load_words<WPL>(p.frt_in + (size_t)xs[u] * W + own * WPL, t[u]);
+#pragma unroll
+                        for (int u = 0; u < kUnroll; ++u)
+#pragma unroll
+                            for (int j = 0; j < WPL; ++j) acc[j] |= t[u][j];
+                    }
+                    for (; a < re; a += LPR) {
+                        uint64_t t[WPL];
+                        load_words<WPL>(p.frt_in + (size_t)p.col[a] * W + own * WPL, t);
+#pragma unroll
+                        for (int j = 0; j < WPL; ++j) acc[j] |= t[j];
+                    }
+                } else if (lane_on) {
                     const uint64_t rb = p.row_ptr[y], re = p.row_ptr[y + 1];
                     uint64_t a = rb;
                     for (; a + kUnroll <= re; a += kUnroll) {
@@ -513,6 +543,19 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                         load_words<WPL>(p.frt_in + (size_t)p.col[a] * W + lig * WPL, t);
 #pragma unroll
                         for (int j = 0; j < WPL; ++j) acc[j] |= t[j];
+                    }
+                }
+                if constexpr (LPR > 1) {
+                    // OR the narrow rows' partial gathers over the lane group
+#pragma unroll
+                    for (int j = 0; j < WPL; ++j) {
+                        uint32_t lo = narrow ? (uint32_t)acc[j] : 0u, hi = narrow ? (uint32_t)(acc[j] >> 32) : 0u;
+#pragma unroll
+                        for (int off = LPR / 2; off > 0; off >>= 1) {
+                            lo |= __shfl_xor(lo, off, 64);
+                            hi |= __shfl_xor(hi, off, 64);
+                        }
+                        if (narrow) acc[j] = lig == own ? ((uint64_t)hi << 32 | lo) : 0ull;
                     }
                 }
                 uint64_t v[WPL], nw[WPL];
