@@ -109,6 +109,53 @@ def cpu_baseline(g, h, budget_s=15.0, seed=0):
                       f"scalar bounded BFS (oracle_hdeg_list), {t_used:.1f} s"}
 
 
+def batched(ctx, count, h, log):
+    """Batched decomposition of `count` Chung-Lu graphs (the first of the
+    256-graph batch: n ~ U{500..20000}, mean degree ~ U[4,16], beta 2.5,
+    seeds 7 + i): autotuned persistent kernel in a hipGraph, then the same
+    graphs one at a time with host-driven rounds; the cores must agree."""
+    import numpy as np
+    import torch
+    from paper_2006_03372_amd import khcore, synth
+    graphs = synth.batch_chung_lu(256)[:count]
+    bg = ctx.batch(graphs)
+    t0 = time.perf_counter()
+    tune = ctx.autotune(bg, h, rounds=32)
+    t_tune = time.perf_counter() - t0
+    log(f"autotune {t_tune:.1f} s: width {tune['width_words']} words, {tune['waves_per_cu']} waves/CU")
+    ctx.set_progress(lambda r, removed, level: log(f"  batched {time.perf_counter() - t0:.0f} s: round {r}, "
+                                                   f"{removed} removed"), 20000)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    core, _, st = ctx.core(bg, h)
+    torch.cuda.synchronize()
+    t_batch = time.perf_counter() - t0
+    ctx.set_progress(None)
+    cb = core.cpu().numpy().view(np.uint32)
+    bg.close()
+    ctx.set_option(khcore.OPT_DRIVER, 0)
+    ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
+    ctx.set_option(khcore.OPT_WAVES_PER_CU, 8)
+    same, off, t_loop = True, 0, 0.0
+    for i, g in enumerate(graphs):
+        gr = ctx.graph(g)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        c, _, _ = ctx.core(gr, h)
+        torch.cuda.synchronize()
+        t_loop += time.perf_counter() - t0
+        same &= bool((c.cpu().numpy().view(np.uint32) == cb[off:off + g.n]).all())
+        off += g.n
+        gr.close()
+        if (i + 1) % 32 == 0:
+            log(f"  loop of single decompositions: {i + 1} graphs, {t_loop:.0f} s")
+    return {"workload": f"{count} Chung-Lu graphs (n ~ U{{500..20000}}, mean ~ U[4,16], beta 2.5), h={h}",
+            "vertices": int(off), "persistent_s": round(t_batch, 2), "rounds": st["rounds"],
+            "autotune": {"width_words": tune["width_words"], "waves_per_cu": tune["waves_per_cu"],
+                         "seconds": round(t_tune, 1)},
+            "loop_of_singles_s": round(t_loop, 2), "speedup": round(t_loop / t_batch, 3), "cores_identical": same}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -121,6 +168,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--decompose-scale", type=int, default=16,
                     help="R-MAT scale of the timed decomposition (0: skip; 20 takes minutes)")
+    ap.add_argument("--batched", type=int, default=0, metavar="COUNT",
+                    help="also time the batched decomposition of COUNT Chung-Lu graphs (256 takes minutes)")
     ap.add_argument("--profile-pass", action="store_true",
                     help="one untimed-warmup-free step without the work count or CPU leg, for profilers")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
@@ -218,6 +267,9 @@ def main():
         ef = 16 if args.decompose_scale >= 20 else 8
         log(f"timing the decomposition of R-MAT scale {args.decompose_scale} at h={h} ...")
         result["decomposition"] = decomposition(ctx, args.decompose_scale, ef, h, log)
+    if args.batched:
+        log(f"timing the batched decomposition of {args.batched} graphs ...")
+        result["batched"] = batched(ctx, args.batched, h, log)
     ctx.close()
     print(json.dumps(result), flush=True)
 

@@ -78,7 +78,7 @@ int khc_destroy(khc_ctx *ctx);
 const char *khc_last_error(const khc_ctx *ctx);
 
 /* Options (khc_set_option).  Values are validated; unknown ids: KHC_EINVAL. */
-#define KHC_OPT_MAX_WIDTH 1       /* max uint64 words per vertex per BFS batch (1..32, pow2; default 16) */
+#define KHC_OPT_MAX_WIDTH 1       /* max uint64 words per vertex per BFS batch (1..32, pow2; default 32) */
 #define KHC_OPT_SCHEDULE 2        /* 0 = plain recompute of the affected set, 1 = bounded (default)     */
 #define KHC_OPT_WORKSPACE_LIMIT 3 /* cap on workspace bytes (0 = none)                                  */
 #define KHC_OPT_VALIDATE 4        /* 1 = validate the CSR in khc_graph_create (default 1)               */

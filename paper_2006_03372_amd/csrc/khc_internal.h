@@ -56,7 +56,7 @@ struct khc_ctx {
     std::string err;
     int sticky = 0;
     // options
-    int max_width = 16;
+    int max_width = 32;
     int schedule = 1;
     uint64_t ws_limit = 0;
     int validate = 1;

@@ -71,3 +71,85 @@ def accuracy(core_exact, core_approx):
     nz = c > 0
     prec = 1.0 - float(np.mean(err[nz] / c[nz])) if nz.any() else 1.0
     return {"exact_fraction": float(np.mean(err == 0)), "mae": float(np.mean(err)), "precision": prec}
+
+
+def evaluate(h=4, train_scale=16, train_edge_factor=8, train_count=32, train_seed=101, test_scale=18,
+             test_edge_factor=8, epochs=10, batch=4096, lr=2e-3, log=print):
+    """Train the network on R-MAT graphs of one scale and peel a larger one
+    exactly, with the network, with the lower bound alone and with an
+    untrained network; returns times and accuracies."""
+    import time
+    from . import khcore, synth
+    torch = _torch()
+    ctx = khcore.Context(0)
+    ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
+    ctx.set_option(khcore.OPT_WAVES_PER_CU, 8)
+    t0 = time.time()
+    graphs = (synth.rmat(train_scale, train_edge_factor, seed=train_seed + i) for i in range(train_count))
+    xs, ts = [], []
+    for i, g in enumerate(graphs):
+        gr = ctx.graph(g)
+        masks, _, _ = states_of(ctx, gr, h)
+        X, t = samples(ctx, gr, h, masks)
+        xs.append(X)
+        ts.append(t)
+        gr.close()
+        log(f"training graph {i + 1}/{train_count}: {X.shape[0]} samples ({time.time() - t0:.0f} s)")
+    X, t = torch.cat(xs).contiguous(), torch.cat(ts).contiguous()
+    del xs, ts
+    net = ctx.mlp(seed=7)
+    t1 = time.time()
+    losses = net.train(X, t, epochs=epochs, batch=batch, lr=lr, seed=1)
+    torch.cuda.synchronize()
+    out = {"h": h, "train": {"graphs": f"R-MAT scale {train_scale} ef {train_edge_factor}, seeds "
+                                       f"{train_seed}..{train_seed + train_count - 1}",
+                             "samples": int(X.shape[0]), "epochs": epochs, "seconds": round(time.time() - t1, 2),
+                             "loss_first": float(losses[0]), "loss_last": float(losses[-1])}}
+    del X, t
+    g = synth.rmat(test_scale, test_edge_factor, seed=1)
+    gr = ctx.graph(g)
+    out["test"] = {"graph": f"R-MAT scale {test_scale} ef {test_edge_factor}, seed 1", "n": g.n,
+                   "edges": g.num_edges}
+
+    def run(name, fn):
+        t2 = time.time()
+        ctx.set_progress(lambda r, removed, level: log(f"  {name}: {time.time() - t2:.0f} s, round {r}, "
+                                                        f"{removed} removed"), 20000)
+        core, st = fn()
+        torch.cuda.synchronize()
+        ctx.set_progress(None)
+        return core.cpu().numpy().view(np.uint32), st, time.time() - t2
+
+    exact, st, te = run("exact", lambda: ctx.core(gr, h)[::2])
+    out["exact"] = {"seconds": round(te, 2), "rounds": st["rounds"], "h_recomputes": st["h_recomputes"]}
+    untrained = ctx.mlp(seed=7)
+    for name, m in (("learned", net), ("lower_bound_only", None), ("untrained", untrained)):
+        core, st, ta = run(name, lambda: ctx.core_approx(gr, h, m)[::2])
+        out[name] = {"seconds": round(ta, 2), "rounds": st["rounds"], "speedup_vs_exact": round(te / ta, 3),
+                     **accuracy(exact, core)}
+        log(f"{name}: {out[name]}")
+    gr.close()
+    ctx.close()
+    return out
+
+
+def main():
+    import argparse
+    import json
+    import sys
+    ap = argparse.ArgumentParser(description="train the learned-mode network and evaluate it against "
+                                             "exact peeling")
+    ap.add_argument("--h", type=int, default=4)
+    ap.add_argument("--train-scale", type=int, default=16)
+    ap.add_argument("--train-count", type=int, default=32)
+    ap.add_argument("--test-scale", type=int, default=18)
+    ap.add_argument("--epochs", type=int, default=10)
+    a = ap.parse_args()
+    out = evaluate(h=a.h, train_scale=a.train_scale, train_count=a.train_count, test_scale=a.test_scale,
+                   test_edge_factor=16 if a.test_scale >= 20 else 8, epochs=a.epochs,
+                   log=lambda m: print(m, file=sys.stderr, flush=True))
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()
