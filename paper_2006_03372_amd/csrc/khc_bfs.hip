@@ -212,29 +212,6 @@ int width_for(uint32_t cnt, int max_width) {
     return w;
 }
 
-// Estimated microseconds of one batch of width W: `levels` pull levels of
-// n (8 + 8W) + nnz (4 + 8W) bytes at 5 TB/s, plus fixed launch costs.
-double batch_cost_us(int W, uint32_t n, uint64_t nnz, uint32_t levels) {
-    const double bytes = (double)n * (8.0 + 8.0 * W) + (double)nnz * (4.0 + 8.0 * W);
-    return levels * (bytes / 5.0e6 + 8.0) + 20.0;
-}
-
-// Width of the next batch for `remaining` sources: the narrowest width that
-// holds them all, unless a full batch of half that width plus a batch for
-// the rest is estimated cheaper (a width-32 batch for 1100 sources reads
-// twice what a width-16 batch for 1024 and a width-2 batch for the rest
-// read).
-int pick_width(uint32_t remaining, int max_width, uint32_t n, uint64_t nnz, uint32_t levels) {
-    const int up = width_for(remaining, max_width);
-    if (up == 1 || (uint64_t)up * 64 < remaining) return up;
-    const int dn = up / 2;
-    const uint32_t rest = remaining - (uint32_t)dn * 64u;
-    const double one = batch_cost_us(up, n, nnz, levels);
-    const double split =
-        batch_cost_us(dn, n, nnz, levels) + batch_cost_us(width_for(rest, max_width), n, nnz, levels);
-    return split < one ? dn : up;
-}
-
 // Batches of up to 64*max_width sources.  Per batch: reset counters, seed,
 // h levels (the scanned-arc mode stops after h-1 and weights the reached
 // rows instead), scatter the per-lane results, clear the touched rows.
@@ -310,7 +287,10 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
                        (int)nq, counts_s[0], 64 * kMaxWidth);
     for (uint32_t first = 0, parity = 0; first < nsrc; parity ^= 1u) {
         const uint32_t remaining = nsrc - first;
-        const int W = pick_width(remaining, maxW, n, g->nnz, levels);
+        // one batch as narrow as holds the rest: a pull level costs a large
+        // fixed part (a latency-bound pass over every row) plus a little per
+        // word, so splitting a batch into narrower ones never pays
+        const int W = width_for(remaining, maxW);
         const uint32_t cnt = remaining < (uint32_t)(64 * W) ? remaining : (uint32_t)(64 * W);
         qdeg = qdeg_s[parity];
         work = work_s[parity];
