@@ -39,3 +39,22 @@ def test_null_context_is_rejected_without_gpu():
     assert lib.khdeg_compute(None, None, None, 2, None) == khcore.KHC_EINVAL
     assert lib.khcore_decompose(None, None, 2, None, None, None) == khcore.KHC_EINVAL
     assert lib.khc_last_error(None) == b"null context"
+
+
+def test_missing_library_fails_loudly(tmp_path, monkeypatch):
+    """No fallback: without the built library the binding raises."""
+    monkeypatch.setattr(khcore, "_lib", None)
+    with pytest.raises(ImportError):
+        khcore.load_library(str(tmp_path / "absent.so"))
+
+
+def test_null_arguments_of_newer_entry_points():
+    if not os.path.exists(khcore.LIB_PATH):
+        pytest.skip("library not built")
+    lib = khcore.load_library()
+    assert lib.khc_autotune(None, None, 3, 8, None) == khcore.KHC_EINVAL
+    assert lib.khc_set_progress(None, khcore.PROGRESS_FN(), None, 100) == khcore.KHC_EINVAL
+    assert lib.khc_persist_profile_read(None, None, None, 0) == khcore.KHC_EINVAL
+    assert lib.khc_mlp_save(None, None, b"x") == khcore.KHC_EINVAL
+    assert lib.khc_mlp_load(None, None, b"x") == khcore.KHC_EINVAL
+    assert lib.khcore_decompose_approx(None, None, 3, None, None, None, None) == khcore.KHC_EINVAL
