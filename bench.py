@@ -59,8 +59,10 @@ def level_source_hash():
     return h.hexdigest()
 
 
-def decomposition(ctx, scale, edge_factor, h, log):
-    """One exact decomposition, host-driven rounds (wall time, statistics)."""
+def decomposition(ctx, scale, edge_factor, h, log, tune=False):
+    """One exact decomposition, host-driven rounds (wall time, statistics);
+    with tune, the width and waves per CU come from khc_autotune (trials cut
+    after 256 rounds, not timed)."""
     import torch
     from paper_2006_03372_amd import khcore, synth
     g = synth.rmat(scale, edge_factor, seed=1)
@@ -68,6 +70,12 @@ def decomposition(ctx, scale, edge_factor, h, log):
     ctx.set_option(khcore.OPT_DRIVER, 0)
     ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
     ctx.set_option(khcore.OPT_WAVES_PER_CU, 8)
+    tuned = None
+    if tune:
+        t0 = time.perf_counter()
+        tuned = ctx.autotune(gr, h, rounds=256)
+        log(f"autotune {time.perf_counter() - t0:.0f} s: width {tuned['width_words']}, "
+            f"{tuned['waves_per_cu']} waves/CU")
     t0 = time.perf_counter()
     ctx.set_progress(lambda r, removed, level: log(f"  decomposition {time.perf_counter() - t0:.0f} s: "
                                                    f"round {r}, {removed} removed, level {level}"), 20000)
@@ -78,8 +86,10 @@ def decomposition(ctx, scale, edge_factor, h, log):
     wall = time.perf_counter() - t0
     ctx.set_progress(None)
     gr.close()
+    setting = ("autotuned: W={}, {} waves/CU".format(tuned["width_words"], tuned["waves_per_cu"]) if tuned
+               else "W=32, 8 waves/CU")
     return {"workload": f"khcore_decompose, R-MAT scale {scale} (ef {edge_factor}, seed 1), h={h}, "
-                        "bounded schedule, host-driven rounds, W=32, 8 waves/CU",
+                        f"bounded schedule, host-driven rounds, {setting}",
             "n": g.n, "edges": g.num_edges, "wall_s": round(wall, 3), "rounds": st["rounds"],
             "h_recomputes": st["h_recomputes"], "hm1_recomputes": st["hm1_recomputes"],
             "max_core": int(core.max().item())}
@@ -168,6 +178,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--decompose-scale", type=int, default=16,
                     help="R-MAT scale of the timed decomposition (0: skip; 20 takes minutes)")
+    ap.add_argument("--tune", action="store_true",
+                    help="autotune width and waves per CU before the timed decomposition")
     ap.add_argument("--batched", type=int, default=0, metavar="COUNT",
                     help="also time the batched decomposition of COUNT Chung-Lu graphs (256 takes minutes)")
     ap.add_argument("--profile-pass", action="store_true",
@@ -266,7 +278,7 @@ def main():
     if args.decompose_scale:
         ef = 16 if args.decompose_scale >= 20 else 8
         log(f"timing the decomposition of R-MAT scale {args.decompose_scale} at h={h} ...")
-        result["decomposition"] = decomposition(ctx, args.decompose_scale, ef, h, log)
+        result["decomposition"] = decomposition(ctx, args.decompose_scale, ef, h, log, tune=args.tune)
     if args.batched:
         log(f"timing the batched decomposition of {args.batched} graphs ...")
         result["batched"] = batched(ctx, args.batched, h, log)

@@ -95,3 +95,30 @@ def test_batch_rejects_foreign_column(ctx):
                                           ctypes.c_void_p(rpt.data_ptr()), ctypes.c_void_p(ct.data_ptr()),
                                           int(rp[-1]), ctypes.byref(h))
     assert rc == khcore.KHC_EGRAPH
+
+
+def test_batch_deep_h_and_closed_forms(ctx):
+    """h = 5 on small graphs, including closed forms (cycles: 2h; complete: n-1)."""
+    graphs = _graphs(6, 20, 200, seed=11) + [synth.cycle(13), synth.cycle(40), synth.complete(7), synth.path(9)]
+    c, r, st, vb = _run(ctx, graphs, 5, 1, 8)
+    for i, g in enumerate(graphs):
+        lo, hi = int(vb[i]), int(vb[i + 1])
+        c_ref, r_ref = oracle.peel(g, 5)
+        assert (c[lo:hi] == c_ref).all(), i
+        assert (r[lo:hi] == r_ref).all(), i
+    assert (c[int(vb[7]):int(vb[8])] == 10).all()   # cycle of 40 at h = 5
+    assert (c[int(vb[8]):int(vb[9])] == 6).all()    # K7
+
+
+def test_batch_with_multi_chunk_hub(ctx):
+    """A star with 9000 leaves (rows of several 4096-arc chunks, pulled and
+    pushed inside its graph's word window) next to small graphs."""
+    graphs = _graphs(5, 100, 1500, seed=12)
+    graphs.insert(2, synth.star(9000))
+    for width in (8, 32):
+        c, r, st, vb = _run(ctx, graphs, 2, 1, width)
+        for i, g in enumerate(graphs):
+            lo, hi = int(vb[i]), int(vb[i + 1])
+            c_ref, r_ref = oracle.peel(g, 2)
+            assert (c[lo:hi] == c_ref).all(), (i, width)
+            assert (r[lo:hi] == r_ref).all(), (i, width)
