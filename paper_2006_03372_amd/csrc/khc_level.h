@@ -65,7 +65,12 @@ __device__ __forceinline__ void store_words(uint64_t *p, const uint64_t (&w)[WPL
 
 constexpr int kPlanes = 8;            // bit-sliced per-lane counters hold up to 255
 constexpr int kUnroll = 8;            // independent gathers in flight per lane
-constexpr int kPushFactor = 16;       // push when frontier arcs * factor < all arcs
+// Push when frontier arcs * factor < all arcs.  A pull level costs a fixed
+// pass over every row plus 8W bytes per arc; a push costs about 8 bytes and
+// one atomic per (frontier arc, non-zero word).  Narrow batches therefore
+// push up to larger frontiers.
+template <int W>
+constexpr int push_factor() { return W >= 32 ? 16 : (W / 2 > 2 ? W / 2 : 2); }
 constexpr int kGrab = 4;              // push work grab: one frontier item per wavefront
 constexpr uint32_t kPushChunk = 256;  // arcs per push item of a heavy frontier row
 constexpr int kStage = 4096;          // LDS staging of frontier rows
@@ -349,7 +354,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
         for (int k = 0; k < kPlanes; ++k) pl[j][k] = 0;
     uint32_t pcount = 0;
 
-    const bool push = (unsigned long long)(*p.qdeg_in) * kPushFactor < (unsigned long long)p.nnz;
+    const bool push = (unsigned long long)(*p.qdeg_in) * push_factor<W>() < (unsigned long long)p.nnz;
     const uint32_t qn_in = *p.qcnt_in;
     const uint32_t hn_in = *p.hcnt_in;
     const uint32_t light_grabs = (qn_in + kGrab - 1) / kGrab;
