@@ -74,10 +74,13 @@ def accuracy(core_exact, core_approx):
 
 
 def evaluate(h=4, train_scale=16, train_edge_factor=8, train_count=32, train_seed=101, test_scale=18,
-             test_edge_factor=8, epochs=10, batch=4096, lr=2e-3, log=print):
-    """Train the network on R-MAT graphs of one scale and peel a larger one
+             test_edge_factor=8, epochs=10, batch=4096, lr=2e-3, log=print, family="rmat", train_n=20000,
+             test_n=200000, mean_degree=8.0):
+    """Train the network on small graphs of one family and peel a larger one
     exactly, with the network, with the lower bound alone and with an
-    untrained network; returns times and accuracies."""
+    untrained network; returns times and accuracies.  family "rmat": R-MAT
+    graphs of train_scale / test_scale; "chung-lu": Chung-Lu graphs (beta
+    2.5, mean_degree) of train_n / test_n vertices."""
     import time
     from . import khcore, synth
     torch = _torch()
@@ -85,7 +88,12 @@ def evaluate(h=4, train_scale=16, train_edge_factor=8, train_count=32, train_see
     ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
     ctx.set_option(khcore.OPT_WAVES_PER_CU, 8)
     t0 = time.time()
-    graphs = (synth.rmat(train_scale, train_edge_factor, seed=train_seed + i) for i in range(train_count))
+    if family == "rmat":
+        graphs = (synth.rmat(train_scale, train_edge_factor, seed=train_seed + i) for i in range(train_count))
+        train_desc = f"R-MAT scale {train_scale} ef {train_edge_factor}"
+    else:
+        graphs = (synth.chung_lu(train_n, mean_degree, 2.5, train_seed + i) for i in range(train_count))
+        train_desc = f"Chung-Lu n={train_n} mean {mean_degree} beta 2.5"
     xs, ts = [], []
     for i, g in enumerate(graphs):
         gr = ctx.graph(g)
@@ -101,15 +109,18 @@ def evaluate(h=4, train_scale=16, train_edge_factor=8, train_count=32, train_see
     t1 = time.time()
     losses = net.train(X, t, epochs=epochs, batch=batch, lr=lr, seed=1)
     torch.cuda.synchronize()
-    out = {"h": h, "train": {"graphs": f"R-MAT scale {train_scale} ef {train_edge_factor}, seeds "
-                                       f"{train_seed}..{train_seed + train_count - 1}",
+    out = {"h": h, "train": {"graphs": f"{train_desc}, seeds {train_seed}..{train_seed + train_count - 1}",
                              "samples": int(X.shape[0]), "epochs": epochs, "seconds": round(time.time() - t1, 2),
                              "loss_first": float(losses[0]), "loss_last": float(losses[-1])}}
     del X, t
-    g = synth.rmat(test_scale, test_edge_factor, seed=1)
+    if family == "rmat":
+        g = synth.rmat(test_scale, test_edge_factor, seed=1)
+        test_desc = f"R-MAT scale {test_scale} ef {test_edge_factor}, seed 1"
+    else:
+        g = synth.chung_lu(test_n, mean_degree, 2.5, 1)
+        test_desc = f"Chung-Lu n={test_n} mean {mean_degree} beta 2.5, seed 1"
     gr = ctx.graph(g)
-    out["test"] = {"graph": f"R-MAT scale {test_scale} ef {test_edge_factor}, seed 1", "n": g.n,
-                   "edges": g.num_edges}
+    out["test"] = {"graph": test_desc, "n": g.n, "edges": g.num_edges}
 
     def run(name, fn):
         t2 = time.time()
@@ -144,10 +155,15 @@ def main():
     ap.add_argument("--train-count", type=int, default=32)
     ap.add_argument("--test-scale", type=int, default=18)
     ap.add_argument("--epochs", type=int, default=10)
+    ap.add_argument("--family", choices=("rmat", "chung-lu"), default="rmat")
+    ap.add_argument("--train-n", type=int, default=20000)
+    ap.add_argument("--test-n", type=int, default=200000)
+    ap.add_argument("--mean-degree", type=float, default=8.0)
     a = ap.parse_args()
     out = evaluate(h=a.h, train_scale=a.train_scale, train_count=a.train_count, test_scale=a.test_scale,
                    test_edge_factor=16 if a.test_scale >= 20 else 8, epochs=a.epochs,
-                   log=lambda m: print(m, file=sys.stderr, flush=True))
+                   log=lambda m: print(m, file=sys.stderr, flush=True), family=a.family, train_n=a.train_n,
+                   test_n=a.test_n, mean_degree=a.mean_degree)
     print(json.dumps(out), flush=True)
 
 
