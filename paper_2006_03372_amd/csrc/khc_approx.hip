@@ -267,7 +267,7 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
         for (uint32_t lev = 1; lev <= h; ++lev)
             hipLaunchKernelGGL(affected_kernel, dim3(wgrid), dim3(256), 0, st, rg, alive, mark, queue, scal, s64,
                                items, (int)lev, (int)h);
-        hipLaunchKernelGGL(kill_kernel, dim3(gn), dim3(256), 0, st, queue, scal, alive);
+        hipLaunchKernelGGL(kill_kernel, dim3(gn), dim3(256), 0, st, queue, scal, alive, (uint32_t *)nullptr, 0);
         hipError_t e = hipMemcpyAsync(hs, scal, (size_t)nscal * 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
         if (e != hipSuccess) return check_hip(ctx, e, "approx round readback");

@@ -183,6 +183,7 @@ enum WsSlot {
     WS_MINPART,
     WS_ITEMS,
     WS_SEG,
+    WS_LBX,
     WS_NUM_SLOTS
 };
 

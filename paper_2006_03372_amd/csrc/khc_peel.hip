@@ -16,12 +16,15 @@
 //
 // Two schedules give identical results (core numbers and removal rounds):
 //  * plain: every affected vertex gets its h-degree recomputed at once;
-//  * bounded (h >= 2): exact (h-1)-degrees dm are maintained (they change
-//    only within h-1 hops of P) and every affected vertex u only becomes
-//    dirty, keeping its old h-degree as an upper bound (h-degrees never
-//    grow as vertices are removed) and the lower bound
-//        lb(u) = max(dm(u), max over live neighbours w of dm(w))
-//    (the closed (h-1)-ball of a neighbour lies inside u's h-ball).  Before
+//  * bounded (h >= 2): lower bounds dm on the (h-1)-degrees are maintained
+//    (exact after each recompute; they change only within h-1 hops of P, are
+//    recomputed within h-2 hops and lowered by |P| at distance h-1, where
+//    only P itself can leave a vertex's (h-1)-ball).  Every affected vertex
+//    u only becomes dirty, keeping its old h-degree as an upper bound
+//    (h-degrees never grow as vertices are removed) and the lower bound
+//        lb(u) = max(dm(u), max over live neighbours w of dm(w), lbx(u))
+//    (the closed (h-1)-ball of a neighbour lies inside u's h-ball; lbx is
+//    the decrement bound of lower_bound_kernel).  Before
 //    each round the level is k = max(k, min over live v of key(v)), key =
 //    d for clean and lb for dirty vertices; dirty vertices with
 //    lb <= k < d are recomputed and the step repeats until none is left
@@ -60,12 +63,22 @@ __global__ void set_flag_kernel(const uint32_t *list, const uint32_t *count, uin
         flag[list[i]] = value;
 }
 
-// lb(u) = max(dm(u), max over live neighbours of dm) for the live vertices
-// u = list[begin .. end) (all vertices when list is null), one wavefront
-// each; the range comes from the round counters (P is queue[0, cnt[0])).
+// Lower bounds of the live vertices u = list[begin .. end) (all vertices
+// when list is null); the range comes from the round counters (P is
+// queue[0, cnt[0]), then the vertices at distance 1, 2, ... h from P).
+// Two bounds, the larger is kept in lb:
+//  * structural: max(dm(u), max over live neighbours w of dm(w));
+//  * decrement (affected vertices only): removing P can cost u only
+//    vertices of P and vertices within h - j hops of P, where j is u's
+//    distance from P (a lost vertex's every short path from u runs through
+//    P), so d(u) falls by at most C(h - j) = |{v : dist(P, v) <= h - j}|.
+//    lbx(u) carries the bound from the last exact value: lbx = d - C when u
+//    was clean, lbx - C when already dirty.  For the outermost ring, j = h,
+//    the drop is at most |P|.
 __global__ void lower_bound_kernel(const uint32_t *list, const uint32_t *s, int h, uint32_t n_all,
                                    const uint64_t *row_ptr, const uint32_t *col, const uint8_t *alive,
-                                   const uint32_t *dm, uint32_t *lb) {
+                                   const uint32_t *dm, uint32_t *lb, const uint8_t *dirty, const uint32_t *d,
+                                   uint32_t *lbx) {
     uint32_t begin = 0, end = n_all;
     if (list) {
         begin = s[R_CNT];
@@ -98,13 +111,27 @@ __global__ void lower_bound_kernel(const uint32_t *list, const uint32_t *s, int 
             const uint32_t o = __shfl_xor(m, off, 64);
             m = o > m ? o : m;
         }
-        if (live && sub == 0) lb[u] = dm[u] > m ? dm[u] : m;
+        if (live && sub == 0) {
+            uint32_t b = dm[u] > m ? dm[u] : m;
+            if (list) {
+                // distance j of queue entry i from P, and C(h - j)
+                uint32_t j = 0, at = s[R_CNT];
+                while (i >= at) at += s[R_CNT + ++j];
+                uint32_t loss = 0;
+                for (int r = 0; r <= h - (int)j; ++r) loss += s[R_CNT + r];
+                const uint32_t base = dirty[u] ? lbx[u] : d[u];
+                const uint32_t x = base > loss ? base - loss : 0u;
+                lbx[u] = x;
+                b = b > x ? b : x;
+            }
+            lb[u] = b;
+        }
     }
 }
 
 struct PeelState {
     uint8_t *alive, *dirty;
-    uint32_t *d, *dm, *lb, *mark, *queue, *list, *s, *part;
+    uint32_t *d, *dm, *lb, *lbx, *mark, *queue, *list, *s, *part;
     unsigned long long *s64;
     uint2 *items;
     int nscal;
@@ -124,7 +151,8 @@ int peel_round_common(khc_ctx *ctx, const khc_graph *g, uint32_t h, const PeelSt
     for (uint32_t lev = 1; lev <= h; ++lev)
         hipLaunchKernelGGL(affected_kernel, dim3(agrid), dim3(256), 0, st, rg, p.alive, p.mark, p.queue, p.s, p.s64,
                            p.items, (int)lev, (int)h);
-    hipLaunchKernelGGL(kill_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, p.alive);
+    hipLaunchKernelGGL(kill_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, p.alive,
+                       bounded ? p.dm : (uint32_t *)nullptr, (int)h);
     hipError_t e = hipMemcpyAsync(ctx->host_scalars, p.s, (size_t)p.nscal * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "peel round readback");
@@ -150,7 +178,7 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     hipStream_t st = ctx->stream;
     const bool bounded = ctx->schedule == 1 && h >= 2;
     int rc;
-    void *alive_v, *dirty_v, *d_v, *dm_v, *lb_v, *mark_v, *queue_v, *list_v, *s_v, *part_v, *items_v;
+    void *alive_v, *dirty_v, *d_v, *dm_v, *lb_v, *lbx_v, *mark_v, *queue_v, *list_v, *s_v, *part_v, *items_v;
     PeelState p;
     p.nscal = round_nscal(h);
     if ((rc = ws_get(ctx, WS_ALIVE, (size_t)n + 8, &alive_v)) ||
@@ -158,6 +186,7 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         (rc = ws_get(ctx, WS_DEG, (size_t)n * 4 + 8, &d_v)) ||
         (rc = ws_get(ctx, WS_DHM1, (size_t)n * 4 + 8, &dm_v)) ||
         (rc = ws_get(ctx, WS_LB, (size_t)n * 4 + 8, &lb_v)) ||
+        (rc = ws_get(ctx, WS_LBX, (size_t)n * 4 + 8, &lbx_v)) ||
         (rc = ws_get(ctx, WS_MARK, (size_t)n * 4 + 8, &mark_v)) ||
         (rc = ws_get(ctx, WS_QUEUE0, (size_t)n * 4 + 8, &queue_v)) ||
         (rc = ws_get(ctx, WS_QUEUE1, (size_t)n * 4 + 8, &list_v)) ||
@@ -170,6 +199,7 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     p.d = (uint32_t *)d_v;
     p.dm = (uint32_t *)dm_v;
     p.lb = (uint32_t *)lb_v;
+    p.lbx = (uint32_t *)lbx_v;
     p.mark = (uint32_t *)mark_v;
     p.queue = (uint32_t *)queue_v;
     p.list = (uint32_t *)list_v;
@@ -193,7 +223,8 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         if ((rc = khdeg_compute(ctx, g, p.alive, h - 1, p.dm))) return rc;
         st_local.hm1_recomputes += n;
         hipLaunchKernelGGL(lower_bound_kernel, dim3(wgrid), dim3(256), 0, st, (const uint32_t *)nullptr, p.s,
-                           (int)h, n, g->row_ptr, g->col, p.alive, p.dm, p.lb);
+                           (int)h, n, g->row_ptr, g->col, p.alive, p.dm, p.lb, (const uint8_t *)p.dirty,
+                           (const uint32_t *)p.d, p.lbx);
     }
 
     uint64_t left = n;
@@ -221,9 +252,9 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         }
         if ((rc = peel_round_common(ctx, g, h, p, bounded, r, core, peel_round, grid_n))) return rc;
         const uint32_t np = hs[R_CNT];
-        uint32_t e_hm1 = 0, e_h = 0;
+        uint32_t e_hm2 = 0, e_h = 0;
         for (uint32_t j = 0; j <= h; ++j) {
-            if (j < h) e_hm1 += hs[R_CNT + j];
+            if (j + 1 < h) e_hm2 += hs[R_CNT + j];
             e_h += hs[R_CNT + j];
         }
         const uint32_t na = e_h - np;
@@ -235,16 +266,18 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
             hipLaunchKernelGGL(finish_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, (int)h, p.mark,
                                (uint8_t *)nullptr, (uint8_t)0);
         } else {
-            // exact (h-1)-degrees change only within h-1 hops of P
-            if (e_hm1 > np) {
-                if ((rc = msbfs_degrees(ctx, g, p.alive, h - 1, p.queue + np, e_hm1 - np, nullptr, 1, p.dm)))
+            // (h-1)-degree bounds change only within h-1 hops of P: recomputed
+            // exactly within h-2 hops; the ring at h-1 lost at most |P| (kill)
+            if (e_hm2 > np) {
+                if ((rc = msbfs_degrees(ctx, g, p.alive, h - 1, p.queue + np, e_hm2 - np, nullptr, 1, p.dm)))
                     return rc;
-                st_local.hm1_recomputes += e_hm1 - np;
+                st_local.hm1_recomputes += e_hm2 - np;
             }
             // bounds and dirtiness change only within h hops of P
             if (na)
                 hipLaunchKernelGGL(lower_bound_kernel, dim3(wgrid), dim3(256), 0, st, p.queue, p.s, (int)h, n,
-                                   g->row_ptr, g->col, p.alive, p.dm, p.lb);
+                                   g->row_ptr, g->col, p.alive, p.dm, p.lb, (const uint8_t *)p.dirty,
+                                   (const uint32_t *)p.d, p.lbx);
             hipLaunchKernelGGL(finish_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, (int)h, p.mark, p.dirty,
                                (uint8_t)1);
         }

@@ -97,7 +97,7 @@ struct PParams {
     unsigned long long *progress;  // host-visible [rounds, removed], or null
     // peeling state
     uint8_t *alive, *dirty;
-    uint32_t *d, *dm, *lb, *mark, *queue, *list, *core, *round;
+    uint32_t *d, *dm, *lb, *lbx, *mark, *queue, *list, *core, *round;
     uint32_t *K, *MIN;
     uint64_t *ahq;  // affected BFS heavy items, per level
     size_t ahq_len;
@@ -254,7 +254,10 @@ __device__ __forceinline__ uint64_t *frt_buf(const PParams &p, uint32_t i) {
 }
 
 // lb(u) = max(dm(u), max over live neighbours of dm), the neighbours read
-// limited to the first kLbArcs; 16 lanes per u.
+// limited to the first kLbArcs; 16 lanes per u.  For the affected vertices
+// (list = the round's queue) also the decrement bound: the last exact
+// h-degree (or carried bound lbx) minus the number of vertices within h - j
+// hops of P, j being u's distance from P.
 __device__ void lower_bounds(const PParams &p, const uint32_t *list, uint32_t begin, uint32_t end,
                              bool mark_dirty) {
     const int lane = threadIdx.x & 63, sub = lane & 15;
@@ -281,7 +284,20 @@ __device__ void lower_bounds(const PParams &p, const uint32_t *list, uint32_t be
             m = o > m ? o : m;
         }
         if (live && sub == 0) {
-            p.lb[u] = p.dm[u] > m ? p.dm[u] : m;
+            uint32_t b = p.dm[u] > m ? p.dm[u] : m;
+            if (list) {
+                // decrement bound: u at distance j from P loses at most the
+                // vertices within h - j hops of P (P included)
+                uint32_t j = 0, at = p.ctl->acnt[0];
+                while (i >= at) at += p.ctl->acnt[++j];
+                uint32_t loss = 0;
+                for (int r = 0; r <= (int)p.h - (int)j; ++r) loss += p.ctl->acnt[r];
+                const uint32_t base = p.dirty[u] ? p.lbx[u] : p.d[u];
+                const uint32_t x = base > loss ? base - loss : 0u;
+                p.lbx[u] = x;
+                b = b > x ? b : x;
+            }
+            p.lb[u] = b;
             if (mark_dirty) p.dirty[u] = 1;
         }
     }
@@ -394,7 +410,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
     // uniform control state
     int phase = PH_INIT;
     Job job{0, 0, nullptr, PH_DONE, false};
-    uint32_t batch = 0, lev = 0, aff_l = 0, np = 0, e_hm1 = 0, e_h = 0;
+    uint32_t batch = 0, lev = 0, aff_l = 0, np = 0, e_hm2 = 0, e_hm1 = 0, e_h = 0;
     auto start_job = [&](uint32_t cnt, uint32_t levels, uint32_t *out, int ret, bool clean) {
         job = Job{cnt, levels, out, ret, clean};
         batch = 0;
@@ -529,15 +545,25 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 break;
             case PH_KILL: {
                 np = ctl->acnt[0];
-                e_hm1 = e_h = 0;
+                e_hm2 = e_hm1 = e_h = 0;
                 for (uint32_t j = 0; j <= h; ++j) {
+                    if (j + 1 < h) e_hm2 += ctl->acnt[j];
                     if (j < h) e_hm1 += ctl->acnt[j];
                     e_h += ctl->acnt[j];
                 }
                 for (size_t i = gtid(); i < np; i += gstride()) p.alive[p.queue[i]] = 0;
+                if (bounded)
+                    // (h-1)-degree bounds of the ring at distance h-1 from P:
+                    // only P itself can leave their (h-1)-balls
+                    for (size_t i = e_hm2 + gtid(); i < e_hm1; i += gstride()) {
+                        const uint32_t u = p.queue[i];
+                        p.dm[u] = p.dm[u] > np ? p.dm[u] - np : 0u;
+                    }
                 {
-                    // sources of the recompute job, grouped by graph
-                    const uint32_t span = (bounded ? e_hm1 : e_h) - np;
+                    // sources of the recompute job, grouped by graph: the
+                    // (h-1)-degrees within h-2 hops of P (bounded) or the
+                    // h-degrees of the whole affected set (plain)
+                    const uint32_t span = (bounded ? e_hm2 : e_h) - np;
                     for (size_t i0 = gtid() - lane; i0 < span; i0 += gstride()) {
                         const size_t i = i0 + lane;
                         const bool take = i < span;
@@ -554,7 +580,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                                            __HIP_MEMORY_SCOPE_SYSTEM);
                     }
                     ctl->stat_aff += e_h - np;
-                    if (bounded) ctl->stat_hm1 += e_hm1 - np;
+                    if (bounded) ctl->stat_hm1 += e_hm2 - np;
                     else ctl->stat_hrec += e_h - np;
                     if (np == 0) {
                         ctl->abort_reason = 1;
@@ -734,7 +760,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 break;
             case PH_KILL:
                 if (bounded)
-                    phase = start_job(e_hm1 - np, h - 1, p.dm, PH_LBD, false);
+                    phase = start_job(e_hm2 - np, h - 1, p.dm, PH_LBD, false);
                 else
                     phase = start_job(e_h - np, h, p.d, PH_UNMARK, false);
                 break;
@@ -809,7 +835,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     const uint32_t fnz_words = (n + 31) / 32;
     const size_t hq_len = (size_t)n + g->nnz / 256 + 1;
     const size_t ahq_len = (size_t)n + g->nnz / kAffChunk + 1;
-    void *vis, *f0, *f1, *f2, *fnz, *hacc, *hdone, *counts, *bq, *bhq, *bctr, *alive, *dirty, *d, *dm, *lb,
+    void *vis, *f0, *f1, *f2, *fnz, *hacc, *hdone, *counts, *bq, *bhq, *bctr, *alive, *dirty, *d, *dm, *lb, *lbx,
         *mark, *queue, *list, *kg, *ming, *ahq, *ctl, *sync, *seg;
     int rc;
     if ((rc = ws_get(ctx, WS_VIS, words * 8, &vis)) || (rc = ws_get(ctx, WS_FRT0, words * 8, &f0)) ||
@@ -826,6 +852,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
         (rc = ws_get(ctx, WS_DEG, (size_t)n * 4 + 8, &d)) ||
         (rc = ws_get(ctx, WS_DHM1, (size_t)n * 4 + 8, &dm)) ||
         (rc = ws_get(ctx, WS_LB, (size_t)n * 4 + 8, &lb)) ||
+        (rc = ws_get(ctx, WS_LBX, (size_t)n * 4 + 8, &lbx)) ||
         (rc = ws_get(ctx, WS_MARK, (size_t)n * 4 + 8, &mark)) ||
         (rc = ws_get(ctx, WS_QUEUE0, (size_t)n * 4 + 8, &queue)) ||
         (rc = ws_get(ctx, WS_QUEUE1, (size_t)n * 4 + 8, &list)) ||
@@ -861,6 +888,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.d = (uint32_t *)d;
     p.dm = (uint32_t *)dm;
     p.lb = (uint32_t *)lb;
+    p.lbx = (uint32_t *)lbx;
     p.mark = (uint32_t *)mark;
     p.queue = (uint32_t *)queue;
     p.list = (uint32_t *)list;

@@ -303,11 +303,23 @@ __global__ void affected_kernel(RoundGraph g, const uint8_t *alive, uint32_t *ma
     }
 }
 
-// Remove P; the level of this round becomes the level.
-__global__ void kill_kernel(const uint32_t *queue, uint32_t *s, uint8_t *alive) {
+// Remove P; the level of this round becomes the level.  With dm (lower
+// bounds on the (h-1)-degrees), the vertices at distance h-1 from P lower
+// their bound by |P|: their (h-1)-ball reaches P only at its rim, so they
+// can lose the vertices of P and nothing else.
+__global__ void kill_kernel(const uint32_t *queue, uint32_t *s, uint8_t *alive, uint32_t *dm, int h) {
     const uint32_t np = s[R_CNT];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x)
         alive[queue[i]] = 0;
+    if (dm && h >= 2) {
+        uint32_t b = 0;
+        for (int j = 0; j + 1 < h; ++j) b += s[R_CNT + j];
+        const uint32_t e = b + s[R_CNT + h - 1];
+        for (uint32_t i = b + blockIdx.x * blockDim.x + threadIdx.x; i < e; i += gridDim.x * blockDim.x) {
+            const uint32_t u = queue[i];
+            dm[u] = dm[u] > np ? dm[u] - np : 0u;
+        }
+    }
     if (blockIdx.x == 0 && threadIdx.x == 0) {
         s[R_K] = s[R_KNEW];
         s[R_LIVE] -= np;
