@@ -285,7 +285,7 @@ __device__ void lower_bounds(const PParams &p, const uint32_t *list, uint32_t be
         }
         if (live && sub == 0) {
             uint32_t b = p.dm[u] > m ? p.dm[u] : m;
-            if (list) {
+            if (list && p.ngraphs == 1) {
                 // decrement bound: u at distance j from P loses at most the
                 // vertices within h - j hops of P (P included)
                 uint32_t j = 0, at = p.ctl->acnt[0];
@@ -551,6 +551,10 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                     if (j < h) e_hm1 += ctl->acnt[j];
                     e_h += ctl->acnt[j];
                 }
+                // the ring counts are over all graphs of a batch, far above any
+                // one graph's: graphs packed together recompute the whole
+                // (h-1)-ball and keep the structural bound alone
+                if (p.ngraphs > 1) e_hm2 = e_hm1;
                 for (size_t i = gtid(); i < np; i += gstride()) p.alive[p.queue[i]] = 0;
                 if (bounded)
                     // (h-1)-degree bounds of the ring at distance h-1 from P:
