@@ -122,6 +122,7 @@ struct PParams {
     const uint64_t *vbase;      // graph offsets [ngraphs + 1] (null: one graph)
     const uint32_t *light_first, *gchunk_first;  // schedule ranges per graph (null: one graph)
     BatchRange *brange;         // what the current batch covers
+    uint32_t *gring;            // graphs packed together: ring sizes [graph][0..h] of the round
     Sync sync;
 };
 
@@ -211,6 +212,35 @@ __device__ void seg_append(const PParams &p, bool take, uint32_t v, uint32_t *to
     if (total && lane == leader) atomicAdd(total, cnt);
 }
 
+// Graphs packed together: count the `take` lanes' vertices (of graph g)
+// in their graph's ring L.  Every lane of the wavefront must call it.
+__device__ void ring_count(const PParams &p, bool take, uint32_t g, uint32_t L) {
+    if (p.ngraphs == 1) return;
+    const uint64_t m = __ballot(take);
+    if (!m) return;
+    const int lane = threadIdx.x & 63;
+    const int leader = __builtin_ctzll(m);
+    const uint32_t gl = __shfl(g, leader, 64);
+    if (__ballot(take && g != gl) == 0ull) {
+        if (lane == leader) atomicAdd(&p.gring[gl * (p.h + 1) + L], (uint32_t)__builtin_popcountll(m));
+    } else if (take) {
+        atomicAdd(&p.gring[g * (p.h + 1) + L], 1u);
+    }
+}
+
+// Size of the rings 0..r around the round's removed set, as seen from
+// vertex u (its own graph's rings when graphs are packed together).
+__device__ __forceinline__ uint32_t ring_total(const PParams &p, uint32_t u, int r) {
+    uint32_t t = 0;
+    if (p.ngraphs == 1) {
+        for (int q = 0; q <= r; ++q) t += p.ctl->acnt[q];
+    } else {
+        const uint32_t *row = p.gring + (size_t)graph_of(p, u) * (p.h + 1);
+        for (int q = 0; q <= r; ++q) t += row[q];
+    }
+    return t;
+}
+
 // Source slot i of the current job: graph g with seg_pfx[g] <= i < seg_pfx[g+1].
 __device__ __forceinline__ uint32_t job_source(const PParams &p, uint32_t i) {
     uint32_t lo = 0, hi = p.ngraphs;
@@ -285,13 +315,12 @@ __device__ void lower_bounds(const PParams &p, const uint32_t *list, uint32_t be
         }
         if (live && sub == 0) {
             uint32_t b = p.dm[u] > m ? p.dm[u] : m;
-            if (list && p.ngraphs == 1) {
+            if (list) {
                 // decrement bound: u at distance j from P loses at most the
                 // vertices within h - j hops of P (P included)
                 uint32_t j = 0, at = p.ctl->acnt[0];
                 while (i >= at) at += p.ctl->acnt[++j];
-                uint32_t loss = 0;
-                for (int r = 0; r <= (int)p.h - (int)j; ++r) loss += p.ctl->acnt[r];
+                const uint32_t loss = ring_total(p, u, (int)p.h - (int)j);
                 const uint32_t base = p.dirty[u] ? p.lbx[u] : p.d[u];
                 const uint32_t x = base > loss ? base - loss : 0u;
                 p.lbx[u] = x;
@@ -358,6 +387,7 @@ __device__ void affected_level(const PParams &p, uint32_t L) {
                     if (L < p.h) add_aff_items(p, L, y);
                 }
             }
+            ring_count(p, take, take ? graph_of(p, y) : 0u, L);
         }
     }
 }
@@ -491,6 +521,8 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                     p.MIN[g] = 0xFFFFFFFFu;
                     p.seg_cnt[g] = 0;
                 }
+                if (p.ngraphs > 1)
+                    for (size_t i = gtid(); i < (size_t)p.ngraphs * (h + 1); i += gstride()) p.gring[i] = 0;
                 if (gtid() == 0) {
                     ctl->rn = 0;
                     for (int i = 0; i < kMaxPersistH + 2; ++i) ctl->acnt[i] = ctl->ahcnt[i] = 0;
@@ -537,6 +569,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                             add_aff_items(p, 0, (uint32_t)v);
                         }
                     }
+                    ring_count(p, take, take ? graph_of(p, (uint32_t)v) : 0u, 0);
                 }
                 break;
             }
@@ -551,17 +584,14 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                     if (j < h) e_hm1 += ctl->acnt[j];
                     e_h += ctl->acnt[j];
                 }
-                // the ring counts are over all graphs of a batch, far above any
-                // one graph's: graphs packed together recompute the whole
-                // (h-1)-ball and keep the structural bound alone
-                if (p.ngraphs > 1) e_hm2 = e_hm1;
                 for (size_t i = gtid(); i < np; i += gstride()) p.alive[p.queue[i]] = 0;
                 if (bounded)
                     // (h-1)-degree bounds of the ring at distance h-1 from P:
                     // only P itself can leave their (h-1)-balls
                     for (size_t i = e_hm2 + gtid(); i < e_hm1; i += gstride()) {
                         const uint32_t u = p.queue[i];
-                        p.dm[u] = p.dm[u] > np ? p.dm[u] - np : 0u;
+                        const uint32_t pu = ring_total(p, u, 0);  // |P| of u's graph
+                        p.dm[u] = p.dm[u] > pu ? p.dm[u] - pu : 0u;
                     }
                 {
                     // sources of the recompute job, grouped by graph: the
@@ -864,7 +894,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
         (rc = ws_get(ctx, WS_AHQ, (size_t)(h + 1) * ahq_len * 8, &ahq)) ||
         (rc = ws_get(ctx, WS_CTL, sizeof(PCtl), &ctl)) ||
         (rc = ws_get(ctx, WS_SYNC, (size_t)(32 + 32 * kXcds) * 4, &sync)) ||
-        (rc = ws_get(ctx, WS_SEG, (size_t)g->ngraphs * 8 + 64 + 32, &seg)))
+        (rc = ws_get(ctx, WS_SEG, (size_t)g->ngraphs * 8 + 64 + 32 + (size_t)g->ngraphs * (h + 1) * 4, &seg)))
         return rc;
     ming = (uint32_t *)kg + g->ngraphs;
     PParams p;
@@ -922,6 +952,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.brange = (BatchRange *)seg;
     p.seg_cnt = (uint32_t *)((char *)seg + 32);
     p.seg_pfx = p.seg_cnt + g->ngraphs;
+    p.gring = p.seg_pfx + g->ngraphs + 1;
     p.vbase = g->vtx_base;
     p.light_first = g->light_first;
     p.gchunk_first = g->graph_chunk_first;
