@@ -196,7 +196,12 @@ int khdeg_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, u
  * level-synchronous peeling: each round removes every live vertex whose
  * h-degree is at most the level k = max(k, min live h-degree), gives it
  * core k, and recomputes the h-degree of the live vertices within h hops
- * of the removed ones (Algorithms 1-2, Observations 1-2).
+ * of the removed ones (Algorithms 1-2, Observations 1-2).  The bounded
+ * schedule (KHC_OPT_SCHEDULE 1, default) recomputes such a vertex only when
+ * its lower bounds reach the level.  The bounds are structural ((h-1)-degrees
+ * of it and its neighbours, after h-LB of Section III) and a decrement bound
+ * (a vertex at distance j from the removed set loses at most the vertices
+ * within h - j hops of that set).  Both schedules give identical results.
  *   h           1..1024 (1..32 with the persistent driver and for graphs
  *               made by khc_graph_create_batched); otherwise KHC_EINVAL
  *   core        device uint32[n] output (isolated vertices: 0)
