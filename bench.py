@@ -1,4 +1,5 @@
-"""Benchmark: h-hop degrees of every vertex of R-MAT scale 20 at h = 3.
+"""Benchmark: h-hop degrees of every vertex of R-MAT scale 20 at h = 3, then
+the exact (k,3)-core decomposition of the same graph.
 
 One step = khdeg_compute over all vertices of the graph (every live vertex
 gets its exact h-hop degree by the multi-source bounded BFS kernels).  The
@@ -6,9 +7,11 @@ throughput is in GTEPS: traversed edges, where the work of one vertex is the
 number of arcs a scalar bounded BFS from it examines (khdeg_scanned_arcs),
 divided by the step time, 10^9 per second.
 
-After the timed steps, the exact (k,h)-core decomposition is timed once on
-R-MAT scale 16 (edge factor 8) at h = 3 (--decompose-scale 20 times the
-R-MAT-20 graph instead, which takes minutes).
+Parity is checked in the same run, outside the timed region: the last
+step's degrees against the CPU oracle on the sampled vertices the CPU
+baseline computes, and the decomposition's core numbers and removal rounds
+by the peeling-order certificate on sampled vertices.  A mismatch exits
+with status 1.
 
 Prints one JSON line.  Only one GPU is used; --gpus above 1 exits.
 """
@@ -23,30 +26,11 @@ sys.path.insert(0, ROOT)
 
 METRIC = "h-hop BFS GTEPS + (k,h)-core wall time, R-MAT-20 h=3; learned-mode error"
 HBM_PEAK_GBS = 8000.0
+LEVEL_PROFILE = os.path.join(ROOT, "profiles", "level_kernel_rmat20_h3.md")
 
 
 def log(msg):
     print(msg, file=sys.stderr, flush=True)
-
-
-def profiled_traffic(path=os.path.join(ROOT, "profiles", "level_kernel_rmat20_h3.md")):
-    """HBM-side bytes per launch of the counting level from the committed
-    rocprofv3 counter summary, or None when the BFS source has changed
-    since the counters were taken."""
-    import hashlib
-    try:
-        text = open(path).read()
-    except OSError:
-        return None
-    vals = {}
-    for line in text.splitlines():
-        line = line.strip()
-        for key in ("traffic_bytes_per_launch:", "source_sha256:"):
-            if line.startswith(key):
-                vals[key] = line.split(":", 1)[1].strip()
-    if vals.get("source_sha256:") != level_source_hash():
-        return None
-    return float(vals["traffic_bytes_per_launch:"])
 
 
 def level_source_hash():
@@ -59,17 +43,100 @@ def level_source_hash():
     return h.hexdigest()
 
 
-def decomposition(ctx, scale, edge_factor, h, log, tune=False):
-    """One exact decomposition, host-driven rounds (wall time, statistics);
-    with tune, the width and waves per CU come from khc_autotune (trials cut
-    after 256 rounds, not timed)."""
+def profiled_counters(path=LEVEL_PROFILE):
+    """Calibrated HBM-side bytes per launch of the counting level from the
+    committed rocprofv3 counter summary (machine-readable lines), or None
+    when the BFS sources have changed since the counters were taken."""
+    try:
+        text = open(path).read()
+    except OSError:
+        return None
+    vals = {}
+    for line in text.splitlines():
+        line = line.strip()
+        if ":" in line:
+            key, val = line.split(":", 1)
+            vals[key.strip()] = val.strip()
+    if vals.get("source_sha256") != level_source_hash() or "traffic_bytes_per_launch" not in vals:
+        return None
+    return float(vals["traffic_bytes_per_launch"])
+
+
+def profiled_traffic(path=LEVEL_PROFILE):
+    return profiled_counters(path)
+
+
+def level_bytes(g, W, last=True):
+    """Per pull launch over the whole graph (no live mask), in bytes:
+    compulsory = what must cross between HBM and the chip if every array the
+    launch touches crosses once: per non-isolated row its schedule entry
+    (4 B), row offset (8 B) and own words (8W B), the column ids (4 B per
+    arc) and the frontier words once (8W B per non-isolated row); a
+    non-counting level also writes the new words (frontier and visited,
+    16W B per row at most, not counted here).
+    modeled = the same rows plus one frontier gather of 8W B per arc, as if
+    no gather hit a cache (the per-arc model of the level)."""
+    import numpy as np
+    rows = int(np.count_nonzero(g.degrees()))
+    compulsory = rows * (4 + 8 + 8 * W) + g.nnz * 4 + rows * 8 * W
+    modeled = rows * (4 + 8 + 8 * W) + g.nnz * (4 + 8 * W)
+    return compulsory, modeled
+
+
+def cpu_baseline(g, h, budget_s=15.0, seed=0):
+    """The oracle's scalar bounded BFS on a bounded random sample of the
+    sources, single thread: traversed edges per second.  Also returns the
+    sampled vertices and their oracle h-degrees for the parity check."""
+    import numpy as np
+    import oracle
+    oracle.build(force=False)
+    deg = g.degrees()
+    cand = np.flatnonzero(deg > 0).astype(np.uint32)
+    rng = np.random.default_rng(seed)
+    order = rng.permutation(cand)
+    done_te, done_v, t_used = 0, 0, 0.0
+    chunk = 16
+    got = []
+    while t_used < budget_s and done_v < order.size:
+        verts = order[done_v:done_v + chunk]
+        t = time.perf_counter()
+        d, te = oracle.hdeg_list(g, h, verts)
+        t_used += time.perf_counter() - t
+        got.append(d)
+        done_te += int(te.sum())
+        done_v += verts.size
+    res = {"value": done_te / t_used / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
+           "sample": f"{done_v} random non-isolated sources of the same graph, h={h}, "
+                     f"scalar bounded BFS (oracle_hdeg_list), {t_used:.1f} s"}
+    return res, order[:done_v], np.concatenate(got)
+
+
+def certificate_check(g, h, core, rnd, count, seed=3):
+    """Peeling-order certificate of the oracle on `count` random
+    non-isolated vertices (conditions (i), (ii)) and on all vertices (iii)."""
+    import numpy as np
+    import oracle
+    rng = np.random.default_rng(seed)
+    cand = np.flatnonzero(g.degrees() > 0).astype(np.uint32)
+    verts = rng.choice(cand, size=min(count, cand.size), replace=False).astype(np.uint32)
+    t = time.perf_counter()
+    fail = oracle.certificate(g, h, core, rnd, verts)
+    return {"vertices": int(verts.size), "violations": [int(x) for x in fail],
+            "cpu_s": round(time.perf_counter() - t, 1)}
+
+
+def decomposition(ctx, g, desc, h, log, tune=False, cert=300):
+    """One exact decomposition, host-driven rounds (wall time, statistics),
+    then the certificate on `cert` sampled vertices (not timed); with tune,
+    the width and waves per CU come from khc_autotune (trials cut after 256
+    rounds, not timed)."""
+    import numpy as np
     import torch
-    from paper_2006_03372_amd import khcore, synth
-    g = synth.rmat(scale, edge_factor, seed=1)
+    from paper_2006_03372_amd import khcore
     gr = ctx.graph(g)
     ctx.set_option(khcore.OPT_DRIVER, 0)
     ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
-    ctx.set_option(khcore.OPT_WAVES_PER_CU, 8)
+    ctx.set_option(khcore.OPT_WAVES_PER_CU, 16)
     tuned = None
     if tune:
         t0 = time.perf_counter()
@@ -81,42 +148,23 @@ def decomposition(ctx, scale, edge_factor, h, log, tune=False):
                                                    f"round {r}, {removed} removed, level {level}"), 20000)
     torch.cuda.synchronize()
     t0 = time.perf_counter()
-    core, _, st = ctx.core(gr, h)
+    core, rnd, st = ctx.core(gr, h, with_round=True)
     torch.cuda.synchronize()
     wall = time.perf_counter() - t0
     ctx.set_progress(None)
     gr.close()
+    c = core.cpu().numpy().view(np.uint32)
+    r = rnd.cpu().numpy().view(np.uint32)
     setting = ("autotuned: W={}, {} waves/CU".format(tuned["width_words"], tuned["waves_per_cu"]) if tuned
-               else "W=32, 8 waves/CU")
-    return {"workload": f"khcore_decompose, R-MAT scale {scale} (ef {edge_factor}, seed 1), h={h}, "
-                        f"bounded schedule, host-driven rounds, {setting}",
-            "n": g.n, "edges": g.num_edges, "wall_s": round(wall, 3), "rounds": st["rounds"],
-            "h_recomputes": st["h_recomputes"], "hm1_recomputes": st["hm1_recomputes"],
-            "max_core": int(core.max().item())}
-
-
-def cpu_baseline(g, h, budget_s=15.0, seed=0):
-    """The oracle's scalar bounded BFS on a bounded random sample of the
-    sources, single thread: traversed edges per second."""
-    import numpy as np
-    import oracle
-    oracle.build(force=False)
-    deg = g.degrees()
-    cand = np.flatnonzero(deg > 0).astype(np.uint32)
-    rng = np.random.default_rng(seed)
-    order = rng.permutation(cand)
-    done_te, done_v, t_used = 0, 0, 0.0
-    chunk = 16
-    while t_used < budget_s and done_v < order.size:
-        verts = order[done_v:done_v + chunk]
-        t = time.perf_counter()
-        _, te = oracle.hdeg_list(g, h, verts)
-        t_used += time.perf_counter() - t
-        done_te += int(te.sum())
-        done_v += verts.size
-    return {"value": done_te / t_used / 1e9, "unit": "GTEPS", "cores": 1, "kind": "oracle",
-            "sample": f"{done_v} random non-isolated sources of the same graph, h={h}, "
-                      f"scalar bounded BFS (oracle_hdeg_list), {t_used:.1f} s"}
+               else "W=32, 16 waves/CU")
+    out = {"workload": f"khcore_decompose, {desc}, h={h}, bounded schedule, host-driven rounds, {setting}",
+           "n": g.n, "edges": g.num_edges, "wall_s": round(wall, 3), "rounds": st["rounds"],
+           "h_recomputes": st["h_recomputes"], "hm1_recomputes": st["hm1_recomputes"],
+           "max_core": int(c.max())}
+    if cert:
+        log(f"certificate on {cert} sampled vertices ...")
+        out["certificate"] = certificate_check(g, h, c, r, cert)
+    return out
 
 
 def batched(ctx, count, h, log):
@@ -166,6 +214,33 @@ def batched(ctx, count, h, log):
             "loop_of_singles_s": round(t_loop, 2), "speedup": round(t_loop / t_batch, 3), "cores_identical": same}
 
 
+def calibrate(kind, mib):
+    """Counter calibration workloads of known size (run under rocprofv3
+    --pmc): a plain device copy of `mib` MiB, or a gather of random 256-byte
+    rows of a `mib` MiB table (as many rows as the table has; the indices
+    add 8 bytes per row)."""
+    import torch
+    nbytes = mib << 20
+    if kind == "copy":
+        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"calibration": "copy", "bytes_read": nbytes, "bytes_written": nbytes, "runs": 3}))
+        return
+    rows = nbytes // 256
+    table = torch.ones((rows, 32), dtype=torch.int64, device="cuda")
+    idx = torch.randint(0, rows, (rows,), dtype=torch.int64, device="cuda",
+                        generator=torch.Generator(device="cuda").manual_seed(1))
+    out = torch.empty_like(table)
+    for _ in range(3):
+        torch.index_select(table, 0, idx, out=out)
+    torch.cuda.synchronize()
+    print(json.dumps({"calibration": "gather", "rows": rows, "bytes_read": rows * (256 + 8),
+                      "bytes_written": rows * 256, "runs": 3}))
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -176,8 +251,10 @@ def main():
     ap.add_argument("--h", type=int, default=3)
     ap.add_argument("--width", type=int, default=32)
     ap.add_argument("--no-cpu", action="store_true")
-    ap.add_argument("--decompose-scale", type=int, default=16,
-                    help="R-MAT scale of the timed decomposition (0: skip; 20 takes minutes)")
+    ap.add_argument("--decompose-scale", type=int, default=20,
+                    help="R-MAT scale of the timed decomposition (0: skip; 20: the benchmark graph itself)")
+    ap.add_argument("--cert", type=int, default=300,
+                    help="sampled vertices of the decomposition's certificate check (0: skip)")
     ap.add_argument("--tune", action="store_true",
                     help="autotune width and waves per CU before the timed decomposition")
     ap.add_argument("--batched", type=int, default=0, metavar="COUNT",
@@ -186,6 +263,8 @@ def main():
                     help="one untimed-warmup-free step without the work count or CPU leg, for profilers")
     ap.add_argument("--calibrate-copy", type=int, default=0, metavar="MIB",
                     help="only run a plain device copy of MIB MiB three times (counter calibration)")
+    ap.add_argument("--calibrate-gather", type=int, default=0, metavar="MIB",
+                    help="only gather random 256-byte rows of a MIB MiB table three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
         print("bench.py runs on one GPU only: this build measures the single-GPU path "
@@ -197,14 +276,9 @@ def main():
     from paper_2006_03372_amd import khcore, synth
 
     if args.calibrate_copy:
-        nbytes = args.calibrate_copy << 20
-        src = torch.ones(nbytes // 4, dtype=torch.int32, device="cuda")
-        dst = torch.empty_like(src)
-        for _ in range(3):
-            dst.copy_(src)
-        torch.cuda.synchronize()
-        print(json.dumps({"calibration_copy_bytes": nbytes, "copies": 3}))
-        return
+        return calibrate("copy", args.calibrate_copy)
+    if args.calibrate_gather:
+        return calibrate("gather", args.calibrate_gather)
     if args.profile_pass:
         args.warmup, args.steps, args.no_cpu, args.decompose_scale = 0, 1, True, 0
 
@@ -246,18 +320,29 @@ def main():
 
     last = prof["level_last"]
     avg_ms = last["ms"] / max(last["launches"], 1)
-    avg_bytes = last["bytes"] / max(last["launches"], 1)
-    achieved = avg_bytes / (avg_ms / 1e3) / 1e9
-    traffic = profiled_traffic() if (args.scale, args.edge_factor, h, args.width) == (20, 16, 3, 32) else None
+    compulsory, modeled = level_bytes(g, args.width)
+    counted = profiled_counters() if (args.scale, args.edge_factor, h, args.width) == (20, 16, 3, 32) else None
+    if counted is not None:
+        achieved = counted / (avg_ms / 1e3) / 1e9
+        basis = "rocprofv3 FETCH_SIZE+WRITE_SIZE per launch (gather-calibrated), committed profile"
+    else:
+        achieved = compulsory / (avg_ms / 1e3) / 1e9
+        basis = "compulsory bytes per launch (no counter profile for the current sources)"
+    frac = achieved / HBM_PEAK_GBS
+    if frac > 1.0:
+        log(f"roofline fraction {frac:.3f} above 1: the byte count is wrong")
+        sys.exit(1)
     roofline = {"bound": "hbm", "achieved": round(achieved, 1), "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                "frac": round(achieved / HBM_PEAK_GBS, 4),
-                "traffic": None if traffic is None else round(traffic / 1e9, 3),
-                "traffic_unit": "GB per launch (rocprofv3 FETCH_SIZE+WRITE_SIZE, copy-calibrated)",
-                "kernel": f"level_kernel<W,LAST> (counting level), {last['launches']} launches, "
-                          f"avg {avg_ms:.3f} ms, {avg_bytes / 1e9:.3f} GB algorithmic per launch"
-                          + ("" if traffic is None else
-                             f"; rocprof FETCH+WRITE {traffic / 1e9:.3f} GB per launch = "
-                             f"{traffic / (avg_ms / 1e3) / 1e9:.0f} GB/s")}
+                "frac": round(frac, 4),
+                "traffic": None if counted is None else round(counted / 1e9, 3),
+                "traffic_unit": "GB per launch",
+                "basis": basis,
+                "kernel": f"level_kernel<{args.width},true> (counting level), {last['launches']} launches, "
+                          f"avg {avg_ms:.3f} ms (HIP events on the library stream)",
+                "compulsory_GB_per_launch": round(compulsory / 1e9, 3),
+                "compulsory_GBs": round(compulsory / (avg_ms / 1e3) / 1e9, 1),
+                "modeled_request_GB_per_launch": round(modeled / 1e9, 3),
+                "modeled_request_GBs": round(modeled / (avg_ms / 1e3) / 1e9, 1)}
 
     result = {
         "metric": METRIC, "value": round(gteps, 2), "unit": "GTEPS", "n_gpus": 1,
@@ -271,19 +356,36 @@ def main():
         "kernels": {k: {"launches": v["launches"], "ms": round(v["ms"], 2)} for k, v in prof.items()},
         "roofline": roofline,
     }
+    bad = False
     if not args.no_cpu:
         log("timing the CPU oracle on a sample ...")
-        result["cpu_baseline"] = cpu_baseline(g, h)
+        base, verts, ref = cpu_baseline(g, h)
+        result["cpu_baseline"] = base
+        got = out.cpu().numpy().view(np.uint32)[verts]
+        mism = int(np.count_nonzero(got != ref))
+        result["parity"] = {"hdeg_sampled_vertices": int(verts.size), "hdeg_mismatches": mism}
+        bad |= mism != 0
     gr.close()
     if args.decompose_scale:
-        ef = 16 if args.decompose_scale >= 20 else 8
-        log(f"timing the decomposition of R-MAT scale {args.decompose_scale} at h={h} ...")
-        result["decomposition"] = decomposition(ctx, args.decompose_scale, ef, h, log, tune=args.tune)
+        if args.decompose_scale == args.scale:
+            dg, desc = g, f"R-MAT scale {args.scale} (ef {args.edge_factor}, seed 1)"
+        else:
+            ef = 16 if args.decompose_scale >= 20 else 8
+            dg, desc = synth.rmat(args.decompose_scale, ef, seed=1), f"R-MAT scale {args.decompose_scale} " \
+                                                                     f"(ef {ef}, seed 1)"
+        log(f"timing the decomposition of {desc} at h={h} ...")
+        result["decomposition"] = decomposition(ctx, dg, desc, h, log, tune=args.tune, cert=args.cert)
+        cert = result["decomposition"].get("certificate")
+        bad |= bool(cert and any(cert["violations"]))
     if args.batched:
         log(f"timing the batched decomposition of {args.batched} graphs ...")
         result["batched"] = batched(ctx, args.batched, h, log)
+        bad |= not result["batched"]["cores_identical"]
     ctx.close()
     print(json.dumps(result), flush=True)
+    if bad:
+        log("PARITY FAILURE: see the parity / certificate fields")
+        sys.exit(1)
 
 
 if __name__ == "__main__":

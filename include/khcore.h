@@ -172,12 +172,19 @@ int khc_validate_csr(khc_ctx *ctx, const khc_csr *g);
  *   alive  device uint8[n] or NULL
  *   h      >= 1
  *   deg    device uint32[n] output; dead vertices get 0
- * Asynchronous on the context stream. */
+ * Returns once the kernels are enqueued, after one small readback (the
+ * number of live vertices that need a BFS); deg is complete when the
+ * context stream has drained. */
 int khdeg_compute(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                   uint32_t *deg);
 
-/* h-degrees of the listed live vertices only: deg[i] = d^h of verts[i].
- *   verts  device uint32[count]; alive as above.  Asynchronous. */
+/* h-degrees of the listed vertices only: deg[i] = d^h of verts[i] (0 for
+ * a dead vertex).
+ *   verts  device uint32[count], each < n (else KHC_EINVAL before any
+ *          kernel reads them); a vertex may be listed more than once
+ *   alive  as above
+ * Returns after a small readback (the id check); deg is complete when the
+ * context stream has drained. */
 int khdeg_compute_list(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                        const uint32_t *verts, uint32_t count, uint32_t *deg);
 
@@ -186,7 +193,8 @@ int khdeg_compute_list(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, u
  * over every live vertex within h-1 hops of v (v included).  Dead vertices
  * get 0.  The paper reports run times only; this count is the work unit
  * its BFS-based h-degree computation performs per vertex.
- *   te     device uint64[n] output.  Asynchronous. */
+ *   te     device uint64[n] output.  Returns after one small readback;
+ *          te is complete when the context stream has drained. */
 int khdeg_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                        uint64_t *te);
 
@@ -259,6 +267,13 @@ int khc_mlp_destroy(khc_mlp *m);
 /* Host float[4801] in/out (also resets the Adam state on set). */
 int khc_mlp_set_params(khc_ctx *ctx, khc_mlp *m, const float *host_params);
 int khc_mlp_get_params(khc_ctx *ctx, const khc_mlp *m, float *host_params, float *host_grad);
+/* Adam state (Kingma and Ba, Algorithm 1): first and second moment
+ * estimates m, v (host float[4801] each, either may be NULL) and the number
+ * of Adam updates made since the parameters were last set (*host_step, may
+ * be NULL).  Update t computes, per parameter, m = 0.9 m + 0.1 g,
+ * v = 0.999 v + 0.001 g^2 and p -= lr (m / (1 - 0.9^t)) / (sqrt(v / (1 - 0.999^t))
+ * + 1e-8) in float32.  Synchronous. */
+int khc_mlp_get_moments(khc_ctx *ctx, const khc_mlp *m, float *host_m, float *host_v, uint64_t *host_step);
 /* Parameters to / from a file: the 8 bytes "KHCMLP01", uint32 4801, then
  * the 4801 float32 parameters in the order above (little endian).  Loading
  * resets the Adam state; a file of another shape gives KHC_EINVAL.

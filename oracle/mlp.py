@@ -15,6 +15,10 @@ Two variants:
     GPU), biases kept in float32, the ReLU derivative read from the rounded
     activation, the hidden-layer gradients rounded to bfloat16 before their
     matrix products.
+
+The optimiser reference is Adam (Kingma and Ba, "Adam: A Method for
+Stochastic Optimization", Algorithm 1) with bias-corrected moments, in
+float64: adam_step().
 """
 from __future__ import annotations
 
@@ -117,3 +121,20 @@ def finite_difference(params, X, t, eps=1e-6, idx=None):
         p[i] = old
         out.append((lp - lm) / (2 * eps))
     return np.array(out)
+
+
+def adam_step(params, grad, m, v, step, lr, beta1=0.9, beta2=0.999, eps=1e-8):
+    """One Adam update (Kingma and Ba, Algorithm 1), float64.
+
+    step is the 1-based index t of this update.  Returns (params', m', v'):
+      m' = beta1 m + (1 - beta1) g
+      v' = beta2 v + (1 - beta2) g^2
+      params' = params - lr * (m' / (1 - beta1^t)) / (sqrt(v' / (1 - beta2^t)) + eps)
+    """
+    p = np.asarray(params, dtype=np.float64)
+    g = np.asarray(grad, dtype=np.float64)
+    m1 = beta1 * np.asarray(m, dtype=np.float64) + (1.0 - beta1) * g
+    v1 = beta2 * np.asarray(v, dtype=np.float64) + (1.0 - beta2) * g * g
+    mhat = m1 / (1.0 - beta1 ** step)
+    vhat = v1 / (1.0 - beta2 ** step)
+    return p - lr * mhat / (np.sqrt(vhat) + eps), m1, v1

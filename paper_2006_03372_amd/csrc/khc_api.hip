@@ -146,6 +146,14 @@ __global__ void fill_u32_kernel(uint32_t *p, uint32_t value, uint64_t count) {
         p[i] = value;
 }
 
+// flags |= 1 if some listed vertex id is >= n.
+__global__ void check_ids_kernel(const uint32_t *verts, uint32_t count, uint32_t n, uint32_t *flags) {
+    bool bad = false;
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x)
+        bad |= verts[i] >= n;
+    if (__ballot(bad) && (threadIdx.x & 63) == 0) atomicOr(flags, 1u);
+}
+
 // Append every live vertex that has a live neighbour (the others have
 // h-degree 0 and need no BFS).  Wave-aggregated atomic append.
 __global__ void compact_sources_kernel(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
@@ -748,6 +756,18 @@ int khdeg_compute_list(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, u
     if (h == 0) return set_error(ctx, KHC_EINVAL, "h must be >= 1");
     if (count == 0) return KHC_OK;
     (void)hipSetDevice(ctx->device);
+    // ids are read on the device: check the range before any kernel uses them
+    int rc;
+    void *flags;
+    if ((rc = ws_get(ctx, WS_FLAGS, 64, &flags))) return rc;
+    hipStream_t st = ctx->stream;
+    hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)flags, 0u, (uint64_t)1);
+    hipLaunchKernelGGL(check_ids_kernel, dim3(grid_for(count, 256, 1024)), dim3(256), 0, st, verts, count, g->n,
+                       (uint32_t *)flags);
+    hipError_t e = hipMemcpyAsync(ctx->host_scalars, flags, 4, hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(ctx, e, "vertex id check");
+    if (ctx->host_scalars[0]) return set_error(ctx, KHC_EINVAL, "a listed vertex id is >= n");
     return msbfs_degrees(ctx, g, alive, h, verts, count, deg, 0, nullptr);
 }
 

@@ -31,7 +31,10 @@ __global__ void batch_reset_kernel(uint32_t *work, uint32_t *qcnt, uint32_t *hcn
 // Put source lane l on its vertex: vis and the level-0 frontier get bit l,
 // and the vertex becomes entry l of the level-0 frontier list.  A dead
 // source is listed but not seeded; its lane stays empty and reports 0.
-// srcs == null means the implicit list first, first+1, ...
+// srcs == null means the implicit list first, first+1, ...  A vertex listed
+// twice is seeded on both lanes and listed twice on the level-0 frontier;
+// pushing a row twice finds no new bits the second time, so both lanes
+// report its h-degree.
 __global__ void batch_seed_kernel(const uint32_t *srcs, uint32_t first, uint32_t cnt, int W,
                                   const uint8_t *alive, const uint64_t *row_ptr, uint64_t *vis,
                                   uint64_t *f0, uint32_t *fnz0, Frontier f) {
@@ -42,9 +45,10 @@ __global__ void batch_seed_kernel(const uint32_t *srcs, uint32_t first, uint32_t
     f.q[l] = s;
     if (alive && !alive[s]) return;
     const uint64_t bit = 1ull << (l & 63);
-    // sources are distinct vertices, so each (vertex, word) has one writer
-    vis[(size_t)s * W + (l >> 6)] |= bit;
-    f0[(size_t)s * W + (l >> 6)] |= bit;
+    // a caller's list may name one vertex twice: two lanes of one word can
+    // then seed the same row, so the bits go in with atomics
+    atomicOr((unsigned long long *)&vis[(size_t)s * W + (l >> 6)], (unsigned long long)bit);
+    atomicOr((unsigned long long *)&f0[(size_t)s * W + (l >> 6)], (unsigned long long)bit);
     atomicOr(&fnz0[s >> 5], 1u << (s & 31));
     const uint64_t ds = row_ptr[s + 1] - row_ptr[s];
     atomicAdd(f.qdeg, (unsigned long long)ds);
@@ -329,8 +333,10 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
             p.counts = (uint32_t *)counts;
             p.nnz = g->nnz;
             p.n = n;
+            // rows without arcs are a suffix of the schedule: they can never
+            // gain a bit, so the pull does not visit them
             p.light_lo = 0;
-            p.light_hi = g->n_light;
+            p.light_hi = g->n_light_nz;
             p.chunk_lo = 0;
             p.chunk_hi = g->n_chunks;
             p.count_keep = 0;

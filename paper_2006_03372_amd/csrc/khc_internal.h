@@ -81,6 +81,7 @@ struct khc_ctx {
     int driver = 0;             // 0 host-driven rounds, 1 one persistent kernel
     int persist_width = 32;     // source words per BFS batch in the persistent kernel
     int barrier_timeout_s = 20; // deadline of one grid-barrier wait
+    int xcd_grouped = 1;        // 0 once a persistent run found a workgroup off XCD blockIdx % 8
     uint64_t wall_clock_khz = 100000;
     struct PersistGraph {
         const khc_graph *g;
@@ -88,10 +89,13 @@ struct khc_ctx {
         int W, grid, bounded, profile;
         uint32_t round_limit;
         uint32_t *core, *round;
+        uint64_t timeout_ticks;  // barrier deadline baked into the captured launch
+        int grouped;             // XCD-grouped (1) or flat (0) barrier
         hipGraphExec_t exec;
         bool same_args(const PersistGraph &o) const {
             return g == o.g && h == o.h && W == o.W && grid == o.grid && bounded == o.bounded &&
-                   profile == o.profile && round_limit == o.round_limit && core == o.core && round == o.round;
+                   profile == o.profile && round_limit == o.round_limit && core == o.core && round == o.round &&
+                   timeout_ticks == o.timeout_ticks && grouped == o.grouped;
         }
     };
     std::vector<PersistGraph> persist_graphs;

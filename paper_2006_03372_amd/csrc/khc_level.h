@@ -153,6 +153,16 @@ __device__ __forceinline__ bool row_window(const LevelParams &p, uint32_t y, int
     return true;
 }
 
+// True when every bit of the lane's words is set in a | b: no gather can
+// add a new bit, so the lane stops gathering.
+template <int WPL>
+__device__ __forceinline__ bool saturated(const uint64_t (&a)[WPL], const uint64_t (&b)[WPL]) {
+    uint64_t all = ~0ull;
+#pragma unroll
+    for (int j = 0; j < WPL; ++j) all &= a[j] | b[j];
+    return all == ~0ull;
+}
+
 // Add the WPL words of x to the bit-sliced counters (one ripple-carry add
 // per word: plane k holds bit k of every bit position's count).
 template <int WPL>
@@ -415,7 +425,10 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
 #pragma unroll
                 for (int j = 0; j < WPL; ++j) acc[j] = 0;
                 uint64_t a = b + group;
-                if (lane_on) {
+                // words this lane's sources have all reached need no gather
+                uint64_t v0[WPL];
+                if (lane_on) load_words<WPL>(p.vis + (size_t)y * W + lig * WPL, v0);
+                if (lane_on && !saturated<WPL>(acc, v0)) {
                     for (; a + (uint64_t)(kUnroll - 1) * GROUPS < e; a += (uint64_t)kUnroll * GROUPS) {
                         uint32_t xs[kUnroll];
 #pragma unroll
@@ -428,6 +441,10 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                         for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
                             for (int j = 0; j < WPL; ++j) acc[j] |= t[u][j];
+                        if (saturated<WPL>(acc, v0)) {
+                            a = e;
+                            break;
+                        }
                     }
                     for (; a < e; a += GROUPS) {
                         uint64_t t[WPL];
@@ -505,6 +522,15 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                 uint64_t acc[WPL];
 #pragma unroll
                 for (int j = 0; j < WPL; ++j) acc[j] = 0;
+                // the row's visited words, read first: a lane whose words
+                // are all set already (every source reached y) gathers nothing
+                uint64_t v[WPL], nw[WPL];
+                if (lane_on) {
+                    load_words<WPL>(p.vis + (size_t)y * W + lig * WPL, v);
+                } else {
+#pragma unroll
+                    for (int j = 0; j < WPL; ++j) v[j] = ~0ull;
+                }
                 if (narrow) {
                     const uint64_t rb = p.row_ptr[y], re = p.row_ptr[y + 1];
                     uint64_t a = rb + lig;
@@ -527,7 +553,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
 #pragma unroll
                         for (int j = 0; j < WPL; ++j) acc[j] |= t[j];
                     }
-                } else if (lane_on) {
+                } else if (lane_on && !saturated<WPL>(acc, v)) {
                     const uint64_t rb = p.row_ptr[y], re = p.row_ptr[y + 1];
                     uint64_t a = rb;
                     for (; a + kUnroll <= re; a += kUnroll) {
@@ -542,6 +568,11 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                         for (int u = 0; u < kUnroll; ++u)
 #pragma unroll
                             for (int j = 0; j < WPL; ++j) acc[j] |= t[u][j];
+                        // every source of the lane's words has reached y
+                        if (saturated<WPL>(acc, v)) {
+                            a = re;
+                            break;
+                        }
                     }
                     for (; a < re; ++a) {
                         uint64_t t[WPL];
@@ -562,13 +593,6 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                         }
                         if (narrow) acc[j] = lig == own ? ((uint64_t)hi << 32 | lo) : 0ull;
                     }
-                }
-                uint64_t v[WPL], nw[WPL];
-                if (lane_on) {
-                    load_words<WPL>(p.vis + (size_t)y * W + lig * WPL, v);
-                } else {
-#pragma unroll
-                    for (int j = 0; j < WPL; ++j) v[j] = ~0ull;
                 }
                 uint64_t any = 0;
 #pragma unroll

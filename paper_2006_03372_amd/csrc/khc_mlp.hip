@@ -425,6 +425,19 @@ int khc_mlp_get_params(khc_ctx *ctx, const khc_mlp *m, float *host_params, float
     return KHC_OK;
 }
 
+int khc_mlp_get_moments(khc_ctx *ctx, const khc_mlp *m, float *host_m, float *host_v, uint64_t *host_step) {
+    if (!ctx) return KHC_EINVAL;
+    if (!m) return set_error(ctx, KHC_EINVAL, "null argument");
+    hipStream_t st = ctx->stream;
+    hipError_t e = hipSuccess;
+    if (host_m) e = hipMemcpyAsync(host_m, m->m, kParams * sizeof(float), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess && host_v) e = hipMemcpyAsync(host_v, m->v, kParams * sizeof(float), hipMemcpyDeviceToHost, st);
+    if (e == hipSuccess) e = hipStreamSynchronize(st);
+    if (e != hipSuccess) return check_hip(ctx, e, "mlp moment download");
+    if (host_step) *host_step = m->step;
+    return KHC_OK;
+}
+
 int khc_mlp_save(khc_ctx *ctx, const khc_mlp *m, const char *path) {
     if (!ctx) return KHC_EINVAL;
     if (!m || !path) return set_error(ctx, KHC_EINVAL, "null argument");

@@ -53,12 +53,16 @@ struct PCtl {
 };
 
 // Workgroups are dispatched to the 8 XCDs round-robin (workgroup b runs on
-// XCD b % 8; checked on the device), and each XCD has its own L2, which is
-// not coherent with the others for ordinary device memory.  The barrier
-// therefore groups workgroups by XCD: members release at workgroup scope
-// (their stores reach the XCD's L2) and, after the barrier, invalidate only
-// their CU's L1; the last arrival of each XCD writes back and invalidates
-// that XCD's L2 once (agent-scope fences) around the global step.
+// XCD b % 8), and each XCD has its own L2, which is not coherent with the
+// others for ordinary device memory.  The barrier therefore groups
+// workgroups by XCD: members release at workgroup scope (their stores reach
+// the XCD's L2) and, after the barrier, invalidate only their CU's L1; the
+// last arrival of each XCD writes back and invalidates that XCD's L2 once
+// (agent-scope fences) around the global step.  Every workgroup reads its
+// hardware XCC id when the kernel starts; if the placement is not b % 8 the
+// run aborts before its first barrier completes and the host reruns it with
+// the flat barrier, in which every workgroup releases and acquires at agent
+// scope (correct on any placement, slower).
 constexpr uint32_t kXcds = 8;
 
 // Barrier words: count[0] global arrivals, gen[0] global generation,
@@ -71,8 +75,15 @@ struct Sync {
     uint32_t *groups;  // group g: groups[g * 32] arrivals, groups[g * 32 + 16] generation
     uint32_t nblocks;
     uint32_t ngroups;
+    uint32_t grouped;  // 1: XCD-grouped barrier, 0: flat barrier
     uint64_t timeout_ticks;
 };
+
+// Abort codes in the abort word (the first to set it wins).
+enum : uint32_t { ABORT_TIMEOUT = 1, ABORT_PLACEMENT = 2 };
+
+// hwreg(HW_REG_XCC_ID, 0, 4): the XCD this wave runs on.
+constexpr int kHwregXccId = 20 | (0 << 6) | ((4 - 1) << 11);
 
 // The graphs a BFS batch covers: their arcs (push/pull choice) and their
 // ranges of the light-row and heavy-chunk schedules.
@@ -132,7 +143,7 @@ __device__ bool wait_change(const Sync &s, const uint32_t *word, uint32_t g) {
     while (__hip_atomic_load(word, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT) == g) {
         if (__hip_atomic_load(s.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) return false;
         if (wall_clock64() - t0 > s.timeout_ticks) {
-            atomicExch(s.abort, 1u);
+            atomicCAS(s.abort, 0u, (uint32_t)ABORT_TIMEOUT);
             return false;
         }
         __builtin_amdgcn_s_sleep(1);
@@ -151,27 +162,39 @@ __device__ bool grid_sync(const Sync &s, uint32_t *s_gen, uint32_t *s_ok) {
     __syncthreads();
     if (threadIdx.x == 0) {
         const uint32_t g = *s_gen;
-        const uint32_t grp = blockIdx.x % kXcds;
-        const uint32_t gsize = s.nblocks / kXcds + (grp < s.nblocks % kXcds ? 1u : 0u);
-        uint32_t *gcount = s.groups + grp * 32;
-        uint32_t *ggen = s.groups + grp * 32 + 16;
         uint32_t ok = 1;
-        __atomic_thread_fence(__ATOMIC_RELEASE);  // workgroup scope: stores reach this XCD's L2
-        if (atomicAdd(gcount, 1u) == gsize - 1) {
-            atomicExch(gcount, 0u);
-            __threadfence();  // write back this XCD's L2
-            if (atomicAdd(s.count, 1u) == s.ngroups - 1) {
+        if (s.grouped) {
+            const uint32_t grp = blockIdx.x % kXcds;
+            const uint32_t gsize = s.nblocks / kXcds + (grp < s.nblocks % kXcds ? 1u : 0u);
+            uint32_t *gcount = s.groups + grp * 32;
+            uint32_t *ggen = s.groups + grp * 32 + 16;
+            // the workgroup's stores have reached this XCD's L2
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+            if (atomicAdd(gcount, 1u) == gsize - 1) {
+                atomicExch(gcount, 0u);
+                __threadfence();  // write back this XCD's L2
+                if (atomicAdd(s.count, 1u) == s.ngroups - 1) {
+                    atomicExch(s.count, 0u);
+                    __threadfence();
+                    atomicAdd(s.gen, 1u);
+                } else {
+                    ok = wait_change(s, s.gen, g) ? 1u : 0u;
+                }
+                __threadfence();  // invalidate this XCD's L2 (and this CU's L1)
+                atomicAdd(ggen, 1u);
+            } else {
+                ok = wait_change(s, ggen, g) ? 1u : 0u;
+                asm volatile("buffer_inv sc0" ::: "memory");  // invalidate this CU's L1
+            }
+        } else {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            if (atomicAdd(s.count, 1u) == s.nblocks - 1) {
                 atomicExch(s.count, 0u);
-                __threadfence();
                 atomicAdd(s.gen, 1u);
             } else {
                 ok = wait_change(s, s.gen, g) ? 1u : 0u;
             }
-            __threadfence();  // invalidate this XCD's L2 (and this CU's L1)
-            atomicAdd(ggen, 1u);
-        } else {
-            ok = wait_change(s, ggen, g) ? 1u : 0u;
-            asm volatile("buffer_inv sc0" ::: "memory");  // invalidate this CU's L1
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
         }
         if (__hip_atomic_load(s.abort, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT)) ok = 0;
         *s_gen = g + 1;
@@ -430,7 +453,13 @@ template <int W>
 __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams p) {
     __shared__ LevelLds<W> sh;
     __shared__ uint32_t s_gen, s_ok, s_ws[kBlockThreads / 64];
-    if (threadIdx.x == 0) s_gen = 0;
+    if (threadIdx.x == 0) {
+        s_gen = 0;
+        // the grouped barrier needs workgroup b on XCD b % 8: check, and
+        // abort before the first barrier completes if it is not so
+        if (p.sync.grouped && (uint32_t)(__builtin_amdgcn_s_getreg(kHwregXccId) & 15) != blockIdx.x % kXcds)
+            atomicCAS(p.sync.abort, 0u, (uint32_t)ABORT_PLACEMENT);
+    }
     const uint32_t n = p.n, h = p.h;
     const bool bounded = p.bounded != 0;
     PCtl *ctl = p.ctl;
@@ -903,7 +932,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.col = g->col;
     p.nnz = g->nnz;
     p.n = n;
-    p.n_light = g->n_light;
+    p.n_light = g->n_light_nz;  // rows without arcs (a suffix) never gain a bit
     p.n_chunks = g->n_chunks;
     p.light_rows = g->light_rows;
     p.heavy_rows = g->heavy_rows;
@@ -972,10 +1001,12 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.sync.ngroups = (uint32_t)grid < kXcds ? (uint32_t)grid : kXcds;
     const uint32_t sync_words = 32 + 32 * p.sync.ngroups;
     p.sync.timeout_ticks = (uint64_t)ctx->wall_clock_khz * 1000ull * (uint64_t)ctx->barrier_timeout_s;
+    p.sync.grouped = ctx->xcd_grouped ? 1u : 0u;
     hipStream_t st = ctx->stream;
 
     // one graph per argument set, replayed on later calls
-    khc_ctx::PersistGraph key{g, h, W, grid, bounded ? 1 : 0, p.profile, p.round_limit, core, peel_round, nullptr};
+    khc_ctx::PersistGraph key{g,           h,         W,       grid, bounded ? 1 : 0, p.profile, p.round_limit,
+                              core,        peel_round, p.sync.timeout_ticks, (int)p.sync.grouped, nullptr};
     hipGraphExec_t exec = nullptr;
     for (auto &e : ctx->persist_graphs)
         if (e.same_args(key)) exec = e.exec;
@@ -1017,6 +1048,12 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     if (e == hipSuccess) e = hipMemcpyAsync(host_sync, sp + 8, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "persistent decomposition");
+    if (host_sync[0] == ABORT_PLACEMENT && ctx->xcd_grouped) {
+        // workgroups are not on XCD blockIdx % 8: rerun with the flat barrier
+        ctx->xcd_grouped = 0;
+        drop_persist_graphs(ctx, nullptr);
+        return persistent_decompose(ctx, g, h, core, peel_round, stats);
+    }
     if (host_sync[0]) {
         if (host_ctl.abort_reason == 1) return set_error(ctx, KHC_ELIMIT, "a round removed no vertex");
         return set_error(ctx, KHC_EHIP, "persistent decomposition aborted: a grid barrier wait exceeded " +

@@ -41,6 +41,7 @@ EXPORTED = [
     "khc_mlp_create", "khc_mlp_destroy", "khc_mlp_set_params", "khc_mlp_get_params",
     "khc_mlp_forward", "khc_mlp_gradient", "khc_mlp_train", "khc_features", "khcore_decompose_approx",
     "khc_persist_profile_read", "khc_set_progress", "khc_autotune", "khc_mlp_save", "khc_mlp_load",
+    "khc_mlp_get_moments",
 ]
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32)
@@ -142,6 +143,7 @@ def load_library(path: str = LIB_PATH):
         "khc_autotune": ([P, P, u32, u32, ctypes.POINTER(Tune)], i32),
         "khc_mlp_save": ([P, P, ctypes.c_char_p], i32),
         "khc_mlp_load": ([P, P, ctypes.c_char_p], i32),
+        "khc_mlp_get_moments": ([P, P, P, P, ctypes.POINTER(ctypes.c_uint64)], i32),
     }
     for name, (args, res) in sig.items():
         f = getattr(lib, name)
@@ -406,6 +408,16 @@ class Mlp:
                                                          p.ctypes.data_as(ctypes.c_void_p),
                                                          g.ctypes.data_as(ctypes.c_void_p)))
         return p, g
+
+    def moments(self):
+        """(m, v, step) of the Adam state."""
+        m = np.zeros(N_PARAMS, dtype=np.float32)
+        v = np.zeros(N_PARAMS, dtype=np.float32)
+        step = ctypes.c_uint64()
+        self.ctx._check(self.ctx.lib.khc_mlp_get_moments(self.ctx.handle, self.handle,
+                                                          m.ctypes.data_as(ctypes.c_void_p),
+                                                          v.ctypes.data_as(ctypes.c_void_p), ctypes.byref(step)))
+        return m, v, int(step.value)
 
     def save(self, path: str):
         self.ctx._check(self.ctx.lib.khc_mlp_save(self.ctx.handle, self.handle, os.fsencode(path)))

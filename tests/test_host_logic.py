@@ -30,11 +30,16 @@ def test_profile_traffic_follows_source_hash(tmp_path, monkeypatch):
     assert bench.profiled_traffic(str(tmp_path / "absent.md")) is None
 
 
-def test_committed_profile_matches_sources():
-    """The committed level-kernel counter summary was taken from the
-    current BFS sources (else bench.py reports traffic as null)."""
+def test_level_byte_counts():
+    """Compulsory and modeled bytes of a pull launch on a small graph, by hand:
+    path 0-1-2 plus an isolated vertex 3 (rows 0..2 non-isolated, 4 arcs)."""
     import bench
-    assert bench.profiled_traffic() is not None
+    from paper_2006_03372_amd import synth
+    g = synth.from_edges(4, [0, 1], [1, 2])
+    comp, model = bench.level_bytes(g, 2)
+    rows, arcs, W = 3, 4, 2
+    assert comp == rows * (4 + 8 + 8 * W) + arcs * 4 + rows * 8 * W
+    assert model == rows * (4 + 8 + 8 * W) + arcs * (4 + 8 * W)
 
 
 def test_bench_refuses_several_gpus():
