@@ -66,6 +66,8 @@ typedef struct {
     uint32_t max_level;       /* largest core number                            */
     uint32_t width_words;     /* source-lane words per vertex of the last batch */
     double wall_ms;           /* host wall time of the call                     */
+    uint64_t local_rounds;    /* rounds that updated h-degrees locally (schedule 2) */
+    uint64_t local_sources;   /* BFS sources of those local updates             */
 } khc_stats;
 
 /* ---- context ---------------------------------------------------------- */
@@ -79,7 +81,9 @@ const char *khc_last_error(const khc_ctx *ctx);
 
 /* Options (khc_set_option).  Values are validated; unknown ids: KHC_EINVAL. */
 #define KHC_OPT_MAX_WIDTH 1       /* max uint64 words per vertex per BFS batch (1..32, pow2; default 32) */
-#define KHC_OPT_SCHEDULE 2        /* 0 = plain recompute of the affected set, 1 = bounded (default)     */
+#define KHC_OPT_SCHEDULE 2        /* 0 = plain recompute of the affected set, 1 = bounded (default),
+                                     2 = local update inside N^h[P] when it is the cheaper of the two
+                                     (host-driven rounds; the persistent driver treats 2 as 0)       */
 #define KHC_OPT_WORKSPACE_LIMIT 3 /* cap on workspace bytes (0 = none)                                  */
 #define KHC_OPT_VALIDATE 4        /* 1 = validate the CSR in khc_graph_create (default 1)               */
 #define KHC_OPT_WAVES_PER_CU 5    /* wavefronts per CU for the BFS level kernels (4..32; default 16)     */
@@ -94,6 +98,10 @@ const char *khc_last_error(const khc_ctx *ctx);
 #define KHC_OPT_ROUND_LIMIT 10    /* stop a decomposition after this many peeling rounds (0 = none,
                                      default): vertices not removed by then keep core 0; used by
                                      the autotuner's trial runs                                      */
+#define KHC_OPT_PUSH_COST 11     /* push/pull choice of a BFS level: 0 = push while the frontier's total
+                                     degree times a width-dependent factor is below the arc count;
+                                     c in 1..4096 = push while (frontier arcs x non-zero source words)
+                                     times c is below (arcs x width + 4 x rows), the pull's gathers */
 int khc_set_option(khc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while KHC_OPT_PROFILE is 1, per kernel class:
@@ -228,6 +236,27 @@ int khcore_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *cor
 int khcore_decompose_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base, const uint64_t *row_ptr,
                              const uint32_t *col, uint64_t nnz, uint32_t h, uint32_t *core,
                              uint32_t *peel_round, khc_stats *stats);
+
+/* ---- sampling-based approximate mode ----------------------------------- */
+
+/* The paper's sampling-based decomposition (Section IV-C, Algorithms 5-6)
+ * in level-synchronous form, on a vertex sample S drawn by the caller.
+ * Each vertex keeps its exact initial h-degree d0, the number sel0 of
+ * sampled vertices within h hops at the start, and the number sel of
+ * sampled vertices within h hops in the current graph; its estimated
+ * h-degree is floor(sel * d0 / sel0), i.e. sel divided by the initial rate
+ * sel0 / d0 (d0 when sel0 = 0).  Peeling runs on the estimate as
+ * khcore_decompose runs on the h-degree, recounting sel for the live
+ * vertices within h hops of each round's removed set.  The estimate never
+ * grows under removal, so the result does not depend on the removal order.
+ *   sampled   device uint8[n]: nonzero marks a sampled vertex
+ *   h         1..1024
+ *   core      device uint32[n] output: the approximate core numbers
+ *   estimate  device uint32[n] or NULL: each vertex's estimate when removed
+ *   stats     host or NULL (h_recomputes counts the ball recounts)
+ * Synchronous (reads a few scalars per round). */
+int khcore_decompose_sampled(khc_ctx *ctx, const khc_graph *g, uint32_t h, const uint8_t *sampled,
+                             uint32_t *core, uint32_t *estimate, khc_stats *stats);
 
 /* ---- autotuner --------------------------------------------------------- */
 

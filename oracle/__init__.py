@@ -10,10 +10,11 @@ Two implementations:
   reference.py   literal Python (brute force over vertex sets, Algorithm 1
                  one vertex at a time, the linear k-core bin sort, a
                  level-synchronous peel) for small graphs;
-  khc_oracle.c   plain single-threaded C (bounded BFS h-degrees, the
-                 level-synchronous peel with from-scratch recomputation and
-                 per-round trace, the peeling-order certificate), loaded
-                 here through ctypes.
+  khc_oracle.c   plain C (bounded BFS h-degrees, the level-synchronous
+                 peel with from-scratch recomputation and per-round trace,
+                 the peeling-order certificate), loaded here through
+                 ctypes; the peel is single-threaded, the per-vertex
+                 loops of hdeg_list and certificate can use OpenMP threads.
 The MLP of the learned approximate mode has its own reference in mlp.py
 (pinned to finite differences).  The approximate decomposition itself has
 no oracle: its output is an estimate whose error the tests measure against
@@ -39,7 +40,7 @@ def build(force: bool = True) -> str:
     """Compile khc_oracle.c into liboracle.so with gcc (single-threaded)."""
     if force or not os.path.exists(_LIB):
         tmp = _LIB + ".tmp"
-        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC",
+        subprocess.check_call(["gcc", "-O2", "-std=c11", "-Wall", "-Wextra", "-fPIC", "-fopenmp",
                                "-shared", "-o", tmp, _SRC])
         os.replace(tmp, _LIB)
     return _LIB
@@ -55,11 +56,12 @@ def _load():
         u32, u64 = ctypes.c_uint32, ctypes.c_uint64
         lib.oracle_check_csr.argtypes = [u32, P, P]
         lib.oracle_hdeg.argtypes = [u32, P, P, P, u32, P]
-        lib.oracle_hdeg_list.argtypes = [u32, P, P, P, u32, P, u64, P, P]
+        lib.oracle_hdeg_list.argtypes = [u32, P, P, P, u32, P, u64, P, P, ctypes.c_int]
         lib.oracle_peel.argtypes = [u32, P, P, u32, P, P, P, P, P, u64, P]
-        lib.oracle_certificate.argtypes = [u32, P, P, u32, P, P, P, u64, P]
+        lib.oracle_certificate.argtypes = [u32, P, P, u32, P, P, P, u64, P, ctypes.c_int]
+        lib.oracle_peel_sampled.argtypes = [u32, P, P, u32, P, P, P]
         for f in (lib.oracle_check_csr, lib.oracle_hdeg, lib.oracle_hdeg_list,
-                  lib.oracle_peel, lib.oracle_certificate):
+                  lib.oracle_peel, lib.oracle_certificate, lib.oracle_peel_sampled):
             f.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -103,15 +105,16 @@ def hdeg(g, h: int, alive=None) -> np.ndarray:
     return out[:n]
 
 
-def hdeg_list(g, h: int, verts, alive=None):
-    """(h-degrees, scanned-arc counts) of the listed vertices only."""
+def hdeg_list(g, h: int, verts, alive=None, threads: int = 1):
+    """(h-degrees, scanned-arc counts) of the listed vertices only; the
+    vertices may be split over `threads` OpenMP threads."""
     n, rp, col = _graph(g)
     a = _alive(alive, n)
     v = np.ascontiguousarray(verts, dtype=np.uint32)
     deg = np.zeros(max(v.size, 1), dtype=np.uint32)
     te = np.zeros(max(v.size, 1), dtype=np.uint64)
     rc = _load().oracle_hdeg_list(n, _ptr(rp), _ptr(col), _ptr(a), h, _ptr(v),
-                                  v.size, _ptr(deg), _ptr(te))
+                                  v.size, _ptr(deg), _ptr(te), int(threads))
     if rc:
         raise MemoryError("oracle_hdeg_list failed")
     return deg[:v.size], te[:v.size]
@@ -140,15 +143,40 @@ def peel(g, h: int, trace: bool = False):
     return core[:n], rnd[:n], np.stack([tk[:r], tp[:r], ta[:r]], axis=1)
 
 
-def certificate(g, h: int, core, rnd, verts=None):
-    """Violation counts of the three peeling-order certificate conditions."""
+def peel_sampled(g, h: int, sampled):
+    """Sampling-based peeling on the vertex sample `sampled` (uint8 mask):
+    (core, estimate at removal), both uint32."""
+    n, rp, col = _graph(g)
+    s = np.ascontiguousarray(sampled, dtype=np.uint8)
+    if s.shape != (n,):
+        raise ValueError("sample mask must have n entries")
+    core = np.zeros(max(n, 1), dtype=np.uint32)
+    est = np.zeros(max(n, 1), dtype=np.uint32)
+    rc = _load().oracle_peel_sampled(n, _ptr(rp), _ptr(col), h, _ptr(s), _ptr(core), _ptr(est))
+    if rc:
+        raise MemoryError("oracle_peel_sampled failed")
+    return core[:n], est[:n]
+
+
+def certificate(g, h: int, core, rnd, verts=None, threads: int = 1):
+    """Violation counts of the three peeling-order certificate conditions
+    ((i) and (ii) on the listed vertices, all when verts is None; (iii) on
+    all), with the vertices split over `threads` OpenMP threads."""
     n, rp, col = _graph(g)
     c = np.ascontiguousarray(core, dtype=np.uint32)
     r = np.ascontiguousarray(rnd, dtype=np.uint32)
     v = None if verts is None else np.ascontiguousarray(verts, dtype=np.uint32)
     fail = np.zeros(3, dtype=np.uint64)
     rc = _load().oracle_certificate(n, _ptr(rp), _ptr(col), h, _ptr(c), _ptr(r),
-                                    _ptr(v), 0 if v is None else v.size, _ptr(fail))
+                                    _ptr(v), 0 if v is None else v.size, _ptr(fail), int(threads))
     if rc:
         raise MemoryError("oracle_certificate failed")
     return fail
+
+
+def host_threads() -> int:
+    """Threads this process may run on (its CPU affinity)."""
+    try:
+        return len(os.sched_getaffinity(0))
+    except AttributeError:
+        return os.cpu_count() or 1

@@ -7,8 +7,11 @@
  * Only the tests, the smoke check and the benchmark's CPU-baseline leg load
  * it.
  *
- * Everything here is single-threaded, integer-only and written directly
- * from the definitions of Section II of the paper:
+ * Everything here is integer-only and written directly from the
+ * definitions of Section II of the paper.  The peel is single-threaded;
+ * the per-vertex loops of oracle_hdeg_list and oracle_certificate may
+ * split their independent vertices over OpenMP threads (each vertex still
+ * gets the same scalar BFS):
  *   - N_v^h(G(S)) = { u in S, u != v : dis_{G(S)}(u, v) <= h }, distances
  *     measured in the subgraph induced by the current vertex set S;
  *   - d_v^h(G(S)) = |N_v^h(G(S))|;
@@ -35,6 +38,12 @@
 #include <stdint.h>
 #include <stdlib.h>
 #include <string.h>
+#ifdef _OPENMP
+#include <omp.h>
+static int og_thread(void) { return omp_get_thread_num(); }
+#else
+static int og_thread(void) { return 0; }
+#endif
 
 typedef struct {
     uint32_t n;
@@ -155,28 +164,52 @@ int oracle_hdeg(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
     return 0;
 }
 
+/* One BFS scratch per thread for the loops over independent vertices. */
+static og_bfs *og_bfs_pool(uint32_t n, int threads) {
+    og_bfs *pool = (og_bfs *)calloc((size_t)threads, sizeof(og_bfs));
+    if (!pool) return NULL;
+    for (int t = 0; t < threads; t++) {
+        if (og_bfs_init(&pool[t], n)) {
+            for (int u = 0; u <= t; u++) og_bfs_free(&pool[u]);
+            free(pool);
+            return NULL;
+        }
+    }
+    return pool;
+}
+
+static void og_bfs_pool_free(og_bfs *pool, int threads) {
+    for (int t = 0; t < threads; t++) og_bfs_free(&pool[t]);
+    free(pool);
+}
+
 /*
  * h-degree of the listed vertices only (deg_out[i] for verts[i]), plus the
  * number of arcs each of those bounded BFS runs scans (te_out, optional).
- * A listed dead vertex gets 0.
+ * A listed dead vertex gets 0.  The vertices are independent: with
+ * threads > 1 they are split over that many OpenMP threads, each running
+ * the same scalar BFS on its own scratch.
  */
 int oracle_hdeg_list(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
                      const uint8_t *alive, uint32_t h, const uint32_t *verts,
-                     uint64_t count, uint32_t *deg_out, uint64_t *te_out) {
+                     uint64_t count, uint32_t *deg_out, uint64_t *te_out, int threads) {
     og_graph g = {n, row_ptr, col};
-    og_bfs b;
-    if (og_bfs_init(&b, n)) return -1;
-    for (uint64_t i = 0; i < count; i++) {
+    if (threads < 1) threads = 1;
+    og_bfs *pool = og_bfs_pool(n, threads);
+    if (!pool) return -1;
+    #pragma omp parallel for num_threads(threads) schedule(dynamic, 4)
+    for (int64_t i = 0; i < (int64_t)count; i++) {
+        og_bfs *b = &pool[og_thread()];
         uint32_t v = verts[i];
         uint64_t te = 0;
         if (alive && !alive[v]) {
             deg_out[i] = 0;
         } else {
-            deg_out[i] = og_hdeg_one(&g, alive, NULL, 0, h, v, &b, te_out ? &te : NULL);
+            deg_out[i] = og_hdeg_one(&g, alive, NULL, 0, h, v, b, te_out ? &te : NULL);
         }
         if (te_out) te_out[i] = te;
     }
-    og_bfs_free(&b);
+    og_bfs_pool_free(pool, threads);
     return 0;
 }
 
@@ -284,18 +317,25 @@ int oracle_peel(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
  */
 int oracle_certificate(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
                        uint32_t h, const uint32_t *c, const uint32_t *rho,
-                       const uint32_t *verts, uint64_t count, uint64_t *fail_out) {
+                       const uint32_t *verts, uint64_t count, uint64_t *fail_out, int threads) {
     og_graph g = {n, row_ptr, col};
-    og_bfs b;
-    if (og_bfs_init(&b, n)) return -1;
-    fail_out[0] = fail_out[1] = fail_out[2] = 0;
-    uint64_t total = verts ? count : n;
-    for (uint64_t i = 0; i < total; i++) {
+    if (threads < 1) threads = 1;
+    og_bfs *pool = og_bfs_pool(n, threads);
+    if (!pool) return -1;
+    uint64_t f0 = 0, f1 = 0;
+    int64_t total = verts ? (int64_t)count : (int64_t)n;
+    /* (i) and (ii) per vertex, independent of each other */
+    #pragma omp parallel for num_threads(threads) schedule(dynamic, 4) reduction(+ : f0, f1)
+    for (int64_t i = 0; i < total; i++) {
+        og_bfs *b = &pool[og_thread()];
         uint32_t v = verts ? verts[i] : (uint32_t)i;
-        if (c[v] > 0 && og_hdeg_one(&g, NULL, c, c[v], h, v, &b, NULL) < c[v]) fail_out[0]++;
-        if (og_hdeg_one(&g, NULL, rho, rho[v], h, v, &b, NULL) > c[v]) fail_out[1]++;
+        if (c[v] > 0 && og_hdeg_one(&g, NULL, c, c[v], h, v, b, NULL) < c[v]) f0++;
+        if (og_hdeg_one(&g, NULL, rho, rho[v], h, v, b, NULL) > c[v]) f1++;
     }
-    og_bfs_free(&b);
+    og_bfs_pool_free(pool, threads);
+    fail_out[0] = f0;
+    fail_out[1] = f1;
+    fail_out[2] = 0;
     /* (iii): for every round value, the claimed cores must be a single
      * value, and non-decreasing in the round.  Bucket by round. */
     uint32_t maxr = 0;
@@ -320,5 +360,106 @@ int oracle_certificate(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
         have = 1;
     }
     free(lo); free(hi); free(seen);
+    return 0;
+}
+
+/*
+ * Sampling-based peeling (Section IV-C, the KHCoreSamp / UpdateHNbrSamp
+ * pair) in level-synchronous form.  sampled[v] != 0 marks the vertex
+ * sample S (drawn by the caller).  For every vertex:
+ *   d0[v]   = exact initial h-degree,
+ *   sel[v]  = |N_v^h(G(alive)) cap S|, the sampled vertices within h hops
+ *             in the current graph (kept exact: the paper subtracts exactly
+ *             the sampled vertices a removal cuts off),
+ *   rate[v] = sel0[v] / d0[v], fixed at the start (sel0 = initial sel),
+ *   est[v]  = sel[v] / rate[v], read here as floor(sel * d0 / sel0) in
+ *             integer arithmetic (the paper's worked example truncates);
+ *             a vertex with sel0 = 0 has no sampled vertex to scale by and
+ *             keeps est = d0.
+ * Peeling then runs on est exactly as oracle_peel runs on the exact
+ * degree: k <- max(k, min est), P = {est <= k}, core[P] = k, and est is
+ * recomputed for the live vertices within h hops of P in the graph before
+ * removal (only their balls can lose sampled vertices).  est never grows
+ * under removal, so the result does not depend on the removal order.
+ * est_out (optional) gets each vertex's estimate when it was removed.
+ * Returns 0 or -1 on allocation failure.
+ */
+static uint32_t og_sampled_in_ball(const og_graph *g, const uint8_t *alive, const uint8_t *sampled,
+                                   uint32_t h, uint32_t v, og_bfs *b) {
+    uint32_t reached = og_hdeg_one(g, alive, NULL, 0, h, v, b, NULL);
+    uint32_t sel = 0;
+    /* the BFS queue holds v and then every vertex it reached */
+    for (uint32_t i = 1; i <= reached; i++) sel += sampled[b->queue[i]] ? 1u : 0u;
+    return sel;
+}
+
+static uint32_t og_estimate(uint32_t sel, uint32_t sel0, uint32_t d0) {
+    if (sel0 == 0) return d0;
+    return (uint32_t)(((uint64_t)sel * d0) / sel0);
+}
+
+int oracle_peel_sampled(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+                        uint32_t h, const uint8_t *sampled, uint32_t *core, uint32_t *est_out) {
+    og_graph g = {n, row_ptr, col};
+    og_bfs b, ab;
+    uint8_t *alive = (uint8_t *)malloc(n ? n : 1);
+    uint32_t *d0 = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t *sel0 = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t *est = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t *P = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    uint32_t *dist = (uint32_t *)malloc((n ? n : 1) * sizeof(uint32_t));
+    if (!alive || !d0 || !sel0 || !est || !P || !dist || og_bfs_init(&b, n) || og_bfs_init(&ab, n)) {
+        free(alive); free(d0); free(sel0); free(est); free(P); free(dist);
+        return -1;
+    }
+    memset(alive, 1, n);
+    for (uint32_t v = 0; v < n; v++) {
+        d0[v] = og_hdeg_one(&g, alive, NULL, 0, h, v, &b, NULL);
+        sel0[v] = og_sampled_in_ball(&g, alive, sampled, h, v, &b);
+        est[v] = d0[v];
+    }
+    uint64_t left = n;
+    uint32_t k = 0;
+    while (left > 0) {
+        uint32_t m = UINT32_MAX;
+        for (uint32_t v = 0; v < n; v++)
+            if (alive[v] && est[v] < m) m = est[v];
+        if (m > k) k = m;
+        uint32_t np = 0;
+        for (uint32_t v = 0; v < n; v++) {
+            if (alive[v] && est[v] <= k) {
+                P[np++] = v;
+                core[v] = k;
+                if (est_out) est_out[v] = est[v];
+            }
+        }
+        /* vertices within h hops of P before removal */
+        og_next_epoch(&ab, n);
+        uint32_t head = 0, tail = 0;
+        for (uint32_t i = 0; i < np; i++) {
+            ab.stamp[P[i]] = ab.epoch;
+            ab.queue[tail++] = P[i];
+            dist[P[i]] = 0;
+        }
+        while (head < tail) {
+            uint32_t x = ab.queue[head++];
+            if (dist[x] >= h) continue;
+            for (uint64_t e = row_ptr[x]; e < row_ptr[x + 1]; e++) {
+                uint32_t y = col[e];
+                if (!alive[y] || ab.stamp[y] == ab.epoch) continue;
+                ab.stamp[y] = ab.epoch;
+                dist[y] = dist[x] + 1;
+                ab.queue[tail++] = y;
+            }
+        }
+        for (uint32_t i = 0; i < np; i++) alive[P[i]] = 0;
+        left -= np;
+        for (uint32_t i = np; i < tail; i++) {
+            uint32_t u = ab.queue[i];
+            est[u] = og_estimate(og_sampled_in_ball(&g, alive, sampled, h, u, &b), sel0[u], d0[u]);
+        }
+    }
+    og_bfs_free(&b); og_bfs_free(&ab);
+    free(alive); free(d0); free(sel0); free(est); free(P); free(dist);
     return 0;
 }

@@ -177,3 +177,131 @@ def level_sync_peel(n, row_ptr, col, h):
         r += 1
     return np.array(core, dtype=np.int64), np.array(rnd, dtype=np.int64), trace
 
+
+
+def brute_core_sampled(n, row_ptr, col, h, sampled):
+    """Core numbers of the sampling-based estimate (Section IV-C), straight
+    from the core definition over every vertex set (small n only).
+
+    With d0 and sel0 the exact h-degree and the number of sampled vertices
+    within h hops in the whole graph, a vertex u of a set T has estimated
+    degree est(u, T) = floor(sel(u, T) * d0(u) / sel0(u)), where sel(u, T)
+    counts the sampled vertices within h hops of u in G(T) (est = d0 when
+    sel0 = 0).  est only shrinks as T shrinks, so the estimated cores nest
+    and core(v) = max over T containing v of min over u in T of est(u, T).
+    """
+    adj = _rows(n, row_ptr, col)
+    full = [True] * n
+    d0 = [len(h_neighbourhood(adj, full, h, v)) for v in range(n)]
+    sel0 = [sum(1 for u in h_neighbourhood(adj, full, h, v) if sampled[u]) for v in range(n)]
+    best = [0] * n
+    for mask in range(1, 1 << n):
+        alive = [(mask >> v) & 1 == 1 for v in range(n)]
+        members = [v for v in range(n) if alive[v]]
+        lo = None
+        for u in members:
+            sel = sum(1 for w in h_neighbourhood(adj, alive, h, u) if sampled[w])
+            e = d0[u] if sel0[u] == 0 else (sel * d0[u]) // sel0[u]
+            lo = e if lo is None or e < lo else lo
+        for v in members:
+            if lo > best[v]:
+                best[v] = lo
+    return np.array(best, dtype=np.uint32)
+
+
+def bitmap_update(n, row_ptr, col, alive, h, v):
+    """h-degree update after deleting one vertex v by reachability inside
+    the ball of v (Section IV-A/B: Observations 1-2, Theorem 1, and the
+    bitmap dynamic programme of Algorithms 3-4), written from the paper's
+    description.
+
+    Returns (labels, region_edges, bitmaps, new_degree):
+      labels       the ball R = N_v^h(G(alive)) relabelled u_0, u_1, ...:
+                   the vertices at distance < h from v first (these own a
+                   bit), each group by increasing vertex id;
+      region_edges the edges of G(R) as (i, j) label pairs, i < j;
+      bitmaps      the reach bitmaps (int, bit j = u_j) after the
+                   initialisation and after each of the h iterations; the
+                   two buffers of the iteration are kept apart (the
+                   programme reads one and writes the other, and both start
+                   from the initial bitmaps);
+      new_degree   {u: h-degree of u in G(alive minus v)} for u in R, from
+                   d(u) - 1 - |{w in R : dist(v, w) <= h - dist(v, u),
+                   w not reachable from u}|.
+    """
+    adj = _rows(n, row_ptr, col)
+    al = [bool(x) for x in alive]
+    dist = {v: 0}
+    q = deque([v])
+    while q:
+        x = q.popleft()
+        if dist[x] == h:
+            continue
+        for y in adj[x]:
+            if al[y] and y not in dist:
+                dist[y] = dist[x] + 1
+                q.append(y)
+    ball = [u for u in dist if u != v]
+    inner = sorted(u for u in ball if dist[u] < h)
+    outer = sorted(u for u in ball if dist[u] == h)
+    labels = inner + outer
+    idx = {u: i for i, u in enumerate(labels)}
+    edges = sorted({(min(idx[a], idx[b]), max(idx[a], idx[b]))
+                    for a in labels for b in adj[a] if b in idx})
+    init = [(1 << i) if i < len(inner) else 0 for i in range(len(labels))]
+    buf = [list(init), list(init)]
+    history = [list(init)]
+    p, qq = 1, 0
+    for _ in range(h):
+        qq, p = p, 1 - p
+        for i, j in edges:
+            buf[qq][i] |= buf[p][j]
+            buf[qq][j] |= buf[p][i]
+        history.append(list(buf[qq]))
+    final = buf[qq]
+    old = hdeg(n, row_ptr, col, al, h)
+    new = {}
+    for u in labels:
+        s = dist[u]
+        lost = 1 + sum(1 for w in labels if dist[w] <= h - s and not (final[idx[u]] >> idx[w]) & 1)
+        new[u] = int(old[u]) - lost
+    return labels, edges, history, new
+
+
+def set_local_update(n, row_ptr, col, alive, h, removed):
+    """New h-degrees of the live vertices within h hops of a removed SET P,
+    computed only inside the region N^h[P] (the set form of the update
+    above, used by the library's local-update rounds).
+
+    With t(w) = dist(P, w) before removal and s = t(u) for an affected u,
+    every vertex u loses exactly the vertices w with t(w) <= h - s that it
+    reaches within h hops before removal but not after; every shortest path
+    of length <= h between such u and w stays inside N^h[P] (before
+    removal) or N^h[P] minus P (after), so both reach tests are made inside
+    the region.  Returns {u: new h-degree}.
+    """
+    adj = _rows(n, row_ptr, col)
+    al = [bool(x) for x in alive]
+    P = set(int(x) for x in removed)
+    t = {p: 0 for p in P}
+    q = deque(P)
+    while q:
+        x = q.popleft()
+        if t[x] == h:
+            continue
+        for y in adj[x]:
+            if al[y] and y not in t:
+                t[y] = t[x] + 1
+                q.append(y)
+    region_pre = [x in t for x in range(n)]
+    region_post = [x in t and x not in P for x in range(n)]
+    old = hdeg(n, row_ptr, col, al, h)
+    new = {}
+    for u, s in t.items():
+        if u in P:
+            continue
+        pre = h_neighbourhood(adj, region_pre, h, u)
+        post = h_neighbourhood(adj, region_post, h, u)
+        lost = sum(1 for w in pre if t[w] <= h - s and w not in post)
+        new[u] = int(old[u]) - lost
+    return new

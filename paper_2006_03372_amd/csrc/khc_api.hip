@@ -155,12 +155,20 @@ __global__ void check_ids_kernel(const uint32_t *verts, uint32_t count, uint32_t
 }
 
 // Append every live vertex that has a live neighbour (the others have
-// h-degree 0 and need no BFS).  Wave-aggregated atomic append.
-__global__ void compact_sources_kernel(uint32_t n, const uint64_t *row_ptr, const uint32_t *col,
+// h-degree 0 and need no BFS), walking the row schedule: heavy rows, then
+// light rows with arcs, each by descending degree.  Wave-aggregated atomic
+// append, so the list is close to that order.  Sources of similar degree
+// then share a BFS batch: the balls of a batch of hubs cover most of the
+// graph and saturate their rows' words early (the pull stops gathering
+// there), and batches of low-degree sources keep small frontiers.
+__global__ void compact_sources_kernel(const uint32_t *heavy_rows, uint32_t n_heavy, const uint32_t *light_rows,
+                                       uint32_t n_light_nz, const uint64_t *row_ptr, const uint32_t *col,
                                        const uint8_t *alive, uint32_t *out, uint32_t *count) {
-    const uint32_t v = blockIdx.x * blockDim.x + threadIdx.x;
+    const uint32_t i = blockIdx.x * blockDim.x + threadIdx.x;
     bool keep = false;
-    if (v < n && (!alive || alive[v])) {
+    uint32_t v = 0;
+    if (i < n_heavy + n_light_nz) v = i < n_heavy ? heavy_rows[i] : light_rows[i - n_heavy];
+    if (i < n_heavy + n_light_nz && (!alive || alive[v])) {
         for (uint64_t e = row_ptr[v]; e < row_ptr[v + 1]; ++e) {
             if (!alive || alive[col[e]]) {
                 keep = true;
@@ -184,6 +192,16 @@ int grid_for(uint64_t count, int threads, int cap) {
     if (g > (uint64_t)cap) g = cap;
     return (int)g;
 }
+
+}  // namespace
+
+void launch_compact(hipStream_t st, const khc_graph *g, const uint8_t *alive, uint32_t *out, uint32_t *count) {
+    const uint32_t rows = g->n_heavy + g->n_light_nz;
+    hipLaunchKernelGGL(compact_sources_kernel, dim3(rows / 256 + 1), dim3(256), 0, st, g->heavy_rows, g->n_heavy,
+                       g->light_rows, g->n_light_nz, g->row_ptr, g->col, alive, out, count);
+}
+
+namespace {
 
 int check_csr_args(khc_ctx *ctx, const khc_csr *g) {
     if (!g) return set_error(ctx, KHC_EINVAL, "csr is null");
@@ -338,7 +356,7 @@ int khc_set_option(khc_ctx *ctx, int option, int64_t value) {
             ctx->max_width = (int)value;
             return KHC_OK;
         case KHC_OPT_SCHEDULE:
-            if (value != 0 && value != 1) return set_error(ctx, KHC_EINVAL, "schedule must be 0 or 1");
+            if (value < 0 || value > 2) return set_error(ctx, KHC_EINVAL, "schedule must be 0, 1 or 2");
             ctx->schedule = (int)value;
             return KHC_OK;
         case KHC_OPT_WORKSPACE_LIMIT:
@@ -367,6 +385,10 @@ int khc_set_option(khc_ctx *ctx, int option, int64_t value) {
         case KHC_OPT_BARRIER_TIMEOUT:
             if (value < 1 || value > 600) return set_error(ctx, KHC_EINVAL, "barrier timeout must be 1..600 s");
             ctx->barrier_timeout_s = (int)value;
+            return KHC_OK;
+        case KHC_OPT_PUSH_COST:
+            if (value < 0 || value > 4096) return set_error(ctx, KHC_EINVAL, "push cost must be in [0, 4096]");
+            ctx->push_cost = (int)value;
             return KHC_OK;
         case KHC_OPT_ROUND_LIMIT:
             if (value < 0 || value > 0xFFFFFFFFll) return set_error(ctx, KHC_EINVAL, "round limit must be >= 0");
@@ -679,8 +701,7 @@ int compact_sources(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint
     if ((rc = ws_get(ctx, WS_SRCS, (size_t)n * 4 + 4, &srcs)) || (rc = ws_get(ctx, WS_FLAGS, 64, &cnt)))
         return rc;
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)cnt, 0u, (uint64_t)1);
-    hipLaunchKernelGGL(compact_sources_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr, g->col,
-                       alive, (uint32_t *)srcs, (uint32_t *)cnt);
+    launch_compact(st, g, alive, (uint32_t *)srcs, (uint32_t *)cnt);
     hipError_t e = hipMemcpyAsync(ctx->host_scalars, cnt, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "source compaction");
@@ -704,24 +725,41 @@ int khdeg_compute(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
     if (!g || !deg) return set_error(ctx, KHC_EINVAL, "graph or output is null");
     if (h == 0) return set_error(ctx, KHC_EINVAL, "h must be >= 1");
     (void)hipSetDevice(ctx->device);
+    return khc::khdeg_compute_impl(ctx, g, alive, h, deg, nullptr, 0);
+}
+
+}  // extern "C"
+
+namespace khc {
+
+int khdeg_compute_impl(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h, uint32_t *deg,
+                       Arena *arena, int arena_width) {
     hipStream_t st = ctx->stream;
     const uint32_t n = g->n;
     if (n == 0) return KHC_OK;
     int rc;
     void *srcs, *cnt;
-    if ((rc = ws_get(ctx, WS_SRCS, (size_t)n * 4, &srcs)) || (rc = ws_get(ctx, WS_FLAGS, 64, &cnt)))
+    if (arena) {
+        srcs = arena->take((size_t)n * 4);
+        cnt = arena->take(64);
+        if (!srcs || !cnt) return set_error(ctx, KHC_ENOMEM, "source list exceeds the caller's scratch region");
+    } else if ((rc = ws_get(ctx, WS_SRCS, (size_t)n * 4, &srcs)) || (rc = ws_get(ctx, WS_FLAGS, 64, &cnt))) {
         return rc;
+    }
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for(n, 256, 4096)), dim3(256), 0, st, deg, 0u,
                        (uint64_t)n);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)cnt, 0u, (uint64_t)1);
-    hipLaunchKernelGGL(compact_sources_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr,
-                       g->col, alive, (uint32_t *)srcs, (uint32_t *)cnt);
+    launch_compact(st, g, alive, (uint32_t *)srcs, (uint32_t *)cnt);
     hipError_t e = hipMemcpyAsync(ctx->host_scalars, cnt, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "source compaction");
     const uint32_t nsrc = ctx->host_scalars[0];
-    return msbfs_degrees(ctx, g, alive, h, (const uint32_t *)srcs, nsrc, nullptr, 1, deg);
+    return msbfs_degrees(ctx, g, alive, h, (const uint32_t *)srcs, nsrc, nullptr, 1, deg, arena, arena_width);
 }
+
+}  // namespace khc
+
+extern "C" {
 
 int khdeg_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                        uint64_t *te) {
@@ -740,8 +778,7 @@ int khdeg_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, u
     hipLaunchKernelGGL(fill_u32_kernel, dim3(grid_for((uint64_t)n * 2, 256, 4096)), dim3(256), 0, st,
                        (uint32_t *)te, 0u, (uint64_t)n * 2);
     hipLaunchKernelGGL(fill_u32_kernel, dim3(1), dim3(64), 0, st, (uint32_t *)cnt, 0u, (uint64_t)1);
-    hipLaunchKernelGGL(compact_sources_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr,
-                       g->col, alive, (uint32_t *)srcs, (uint32_t *)cnt);
+    launch_compact(st, g, alive, (uint32_t *)srcs, (uint32_t *)cnt);
     hipError_t e = hipMemcpyAsync(ctx->host_scalars, cnt, 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "source compaction");

@@ -23,7 +23,8 @@ __global__ void batch_reset_kernel(uint32_t *work, uint32_t *qcnt, uint32_t *hcn
         work[i] = 0;
         qcnt[i] = 0;
         hcnt[i] = 0;
-        qdeg[i] = 0;
+        qdeg[2 * i] = 0;
+        qdeg[2 * i + 1] = 0;
     }
     for (int i = threadIdx.x; i < ncounts; i += blockDim.x) counts[i] = 0;
 }
@@ -52,6 +53,7 @@ __global__ void batch_seed_kernel(const uint32_t *srcs, uint32_t first, uint32_t
     atomicOr(&fnz0[s >> 5], 1u << (s & 31));
     const uint64_t ds = row_ptr[s + 1] - row_ptr[s];
     atomicAdd(f.qdeg, (unsigned long long)ds);
+    atomicAdd(f.qdeg + 1, (unsigned long long)ds);  // one non-zero word per seeded lane
     add_push_items(f, s, ds);
 }
 
@@ -109,7 +111,8 @@ __global__ void batch_end_kernel(BatchEnd b) {
         b.nwork[i] = 0;
         b.nqcnt[i] = 0;
         b.nhcnt[i] = 0;
-        b.nqdeg[i] = 0;
+        b.nqdeg[2 * i] = 0;
+        b.nqdeg[2 * i + 1] = 0;
     }
     for (size_t i = gt; i < b.ncounts_len; i += gs) b.ncounts[i] = 0;
 }
@@ -179,6 +182,30 @@ __global__ void te_scatter_kernel(const uint32_t *srcs, uint32_t first, uint32_t
     te_full[s] = te[l];
 }
 
+// Row-count mode (the local h-degree update): after the last level of a
+// batch, every listed row u adds the number of this batch's lanes that
+// reached it and whose source index is below limit(u), the end of the
+// sources at distance <= h - s(u) from the removed set, s(u) = mark[u] - 1
+// (sources are listed by that distance; lvl[j] counts those at distance j).
+__global__ void row_count_kernel(RowCount rc, const uint64_t *vis, int W, uint32_t first) {
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < rc.nrows; i += gridDim.x * blockDim.x) {
+        const uint32_t u = rc.rows[i];
+        const uint32_t s = rc.mark[u] - 1u;
+        uint32_t limit = 0;
+        for (uint32_t j = 0; j + s <= rc.h; ++j) limit += rc.lvl[j];
+        if (limit <= first) continue;
+        const uint32_t span = limit - first;  // lanes [0, span) of this batch count
+        uint32_t c = 0;
+        for (int w = 0; w < W && (uint32_t)w * 64u < span; ++w) {
+            uint64_t bits = vis[(size_t)u * W + w];
+            const uint32_t left = span - (uint32_t)w * 64u;
+            if (left < 64u) bits &= (1ull << left) - 1ull;
+            c += (uint32_t)__builtin_popcountll(bits);
+        }
+        if (c) rc.acc[u] += c;
+    }
+}
+
 __global__ void zero_u64_kernel(unsigned long long *p, int count) {
     for (int i = threadIdx.x; i < count; i += blockDim.x) p[i] = 0;
 }
@@ -219,45 +246,75 @@ int width_for(uint32_t cnt, int max_width) {
 // Batches of up to 64*max_width sources.  Per batch: reset counters, seed,
 // h levels (the scanned-arc mode stops after h-1 and weights the reached
 // rows instead), scatter the per-lane results, clear the touched rows.
+// Buffers of the multi-source BFS, in this order: vis, three frontier
+// buffers, frontier maps, heavy-row accumulators and completion counters,
+// per-lane counts, counters, frontier lists, push items, list table, and
+// scanned-arc totals (te mode only).
+enum { B_VIS, B_F0, B_F1, B_F2, B_FNZ, B_HACC, B_HDONE, B_COUNTS, B_MISC, B_QUEUES, B_HQUEUES, B_QPTRS, B_TE, B_NUM };
+const int kBufSlot[B_NUM] = {WS_VIS,  WS_FRT0,   WS_FRT1,   WS_FRT2,    WS_FNZ,    WS_HACC, WS_HDONE,
+                             WS_COUNTS, WS_MISC, WS_BQUEUE, WS_HQUEUE, WS_QPTRS, WS_TE};
+
+void msbfs_sizes(const khc_graph *g, uint32_t nq, int maxW, bool te, size_t *sz) {
+    const uint32_t n = g->n;
+    const size_t words = (size_t)n * maxW;
+    const uint32_t fnz_words = (n + 31) / 32;
+    // push items per level: at most one per row plus one per kPushChunk arcs
+    const size_t hq_len = (size_t)n + g->nnz / kPushChunk + 1;
+    sz[B_VIS] = sz[B_F0] = sz[B_F1] = sz[B_F2] = words * 8;
+    sz[B_FNZ] = (size_t)fnz_words * 3 * 4;
+    sz[B_HACC] = ((size_t)g->n_heavy + 1) * maxW * 8;
+    sz[B_HDONE] = ((size_t)g->n_heavy + 1) * 4;
+    sz[B_COUNTS] = (size_t)2 * 64 * kMaxWidth * 4;
+    sz[B_MISC] = (size_t)2 * (nq * 32 + 64);
+    sz[B_QUEUES] = (size_t)nq * n * 4 + 4;
+    sz[B_HQUEUES] = (size_t)nq * hq_len * 8;
+    sz[B_QPTRS] = (size_t)nq * 8;
+    sz[B_TE] = te ? (size_t)64 * kMaxWidth * 8 : 0;
+}
+
 int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
               const uint32_t *srcs, uint32_t nsrc, uint32_t *deg_list, int scatter,
-              uint32_t *deg_full, uint64_t *te_full, uint32_t *const *level_out = nullptr) {
+              uint32_t *deg_full, uint64_t *te_full, uint32_t *const *level_out = nullptr,
+              Arena *arena = nullptr, int arena_width = 0, const uint8_t *count_mask = nullptr,
+              const RowCount *row_count = nullptr) {
     if (nsrc == 0) return KHC_OK;
     const uint32_t levels = te_full ? h - 1 : h;
     const uint32_t n = g->n;
-    const int maxW = ctx->max_width;
-    const size_t words = (size_t)n * maxW;
+    const int maxW = arena ? arena_width : ctx->max_width;
     const uint32_t fnz_words = (n + 31) / 32;
     const uint32_t nq = levels + 1;  // frontier lists 0..levels
-    void *vis, *f0, *f1, *f2, *fnz, *hacc, *hdone, *counts, *misc, *queues, *hqueues, *qptrs;
-    // push items per level: at most one per row plus one per kPushChunk arcs
     const size_t hq_len = (size_t)n + g->nnz / kPushChunk + 1;
-    int rc;
-    if ((rc = ws_get(ctx, WS_VIS, words * 8, &vis)) ||
-        (rc = ws_get(ctx, WS_FRT0, words * 8, &f0)) ||
-        (rc = ws_get(ctx, WS_FRT1, words * 8, &f1)) ||
-        (rc = ws_get(ctx, WS_FRT2, words * 8, &f2)) ||
-        (rc = ws_get(ctx, WS_FNZ, (size_t)fnz_words * 3 * 4, &fnz)) ||
-        (rc = ws_get(ctx, WS_HACC, ((size_t)g->n_heavy + 1) * maxW * 8, &hacc)) ||
-        (rc = ws_get(ctx, WS_HDONE, ((size_t)g->n_heavy + 1) * 4, &hdone)) ||
-        (rc = ws_get(ctx, WS_COUNTS, (size_t)2 * 64 * kMaxWidth * 4, &counts)) ||
-        (rc = ws_get(ctx, WS_MISC, (size_t)2 * (nq * 24 + 64), &misc)) ||
-        (rc = ws_get(ctx, WS_BQUEUE, (size_t)nq * n * 4 + 4, &queues)) ||
-        (rc = ws_get(ctx, WS_HQUEUE, (size_t)nq * hq_len * 8, &hqueues)) ||
-        (rc = ws_get(ctx, WS_QPTRS, (size_t)nq * 8, &qptrs)))
-        return rc;
-    void *te = nullptr;
-    if (te_full && (rc = ws_get(ctx, WS_TE, (size_t)64 * kMaxWidth * 8, &te))) return rc;
+    size_t sz[B_NUM];
+    msbfs_sizes(g, nq, maxW, te_full != nullptr, sz);
+    void *buf[B_NUM] = {};
+    for (int b = 0; b < B_NUM; ++b) {
+        if (!sz[b]) continue;
+        if (!arena) {
+            int rc = ws_get(ctx, kBufSlot[b], sz[b], &buf[b]);
+            if (rc) return rc;
+        } else if (!(buf[b] = arena->take(sz[b]))) {
+            return set_error(ctx, KHC_ENOMEM, "BFS buffers exceed the caller's scratch region");
+        }
+    }
+    if (arena) {
+        // a carved region holds whatever its last user left: the buffers the
+        // levels expect to start zero are cleared here
+        for (int b : {B_VIS, B_F0, B_F1, B_F2, B_FNZ, B_HACC, B_HDONE})
+            fill_u32(ctx, (uint32_t *)buf[b], 0u, sz[b] / 4);
+    }
+    void *vis = buf[B_VIS], *f0 = buf[B_F0], *f1 = buf[B_F1], *f2 = buf[B_F2], *fnz = buf[B_FNZ];
+    void *hacc = buf[B_HACC], *hdone = buf[B_HDONE], *counts = buf[B_COUNTS], *misc = buf[B_MISC];
+    void *queues = buf[B_QUEUES], *hqueues = buf[B_HQUEUES], *qptrs = buf[B_QPTRS], *te = buf[B_TE];
     uint64_t *frt[3] = {(uint64_t *)f0, (uint64_t *)f1, (uint64_t *)f2};
     uint32_t *fnzp = (uint32_t *)fnz;
     // Two counter sets, used by alternate batches (the end of a batch zeros
-    // the other): misc = [set 0: qdeg[nq] (u64), work, qcnt, hcnt (u32)]
-    // then set 1; counts = per-lane totals of set 0 then set 1.
+    // the other): misc = [set 0: qdeg[2 nq] (u64 pairs), work, qcnt, hcnt
+    // (u32)] then set 1; counts = per-lane totals of set 0 then set 1.
     unsigned long long *qdeg_s[2];
     uint32_t *work_s[2], *qcnt_s[2], *hcnt_s[2], *counts_s[2];
     for (int ps = 0; ps < 2; ++ps) {
-        qdeg_s[ps] = (unsigned long long *)((char *)misc + (size_t)ps * (nq * 24 + 64));
-        work_s[ps] = (uint32_t *)(qdeg_s[ps] + nq);
+        qdeg_s[ps] = (unsigned long long *)((char *)misc + (size_t)ps * (nq * 32 + 64));
+        work_s[ps] = (uint32_t *)(qdeg_s[ps] + 2 * nq);
         qcnt_s[ps] = work_s[ps] + nq;
         hcnt_s[ps] = qcnt_s[ps] + nq;
         counts_s[ps] = (uint32_t *)counts + (size_t)ps * 64 * kMaxWidth;
@@ -271,7 +328,7 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
         Frontier f;
         f.q = Q(j);
         f.qcnt = qcnt + j;
-        f.qdeg = qdeg + j;
+        f.qdeg = qdeg + 2 * j;
         f.hq = hqbase + (size_t)j * hq_len;
         f.hcnt = hcnt + j;
         return f;
@@ -333,6 +390,8 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
             p.counts = (uint32_t *)counts;
             p.nnz = g->nnz;
             p.n = n;
+            p.push_cost = (uint32_t)ctx->push_cost;
+            p.count_mask = count_mask;
             // rows without arcs are a suffix of the schedule: they can never
             // gain a bit, so the pull does not visit them
             p.light_lo = 0;
@@ -346,8 +405,9 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
             // algorithmic bytes of a pull level over the whole graph
             const double bytes = alive ? 0.0
                                        : (double)n * (8.0 + 8.0 * W) + (double)g->nnz * (4.0 + 8.0 * W);
-            const bool last = !te_full && lev == h;
-            const int prec = prof_begin(ctx, last ? 3 : (lev == 1 ? 1 : 2), bytes);
+            // row-count mode reads vis after the last level, so every level writes it
+            const bool last = !te_full && !row_count && lev == h;
+            const int prec = arena ? -1 : prof_begin(ctx, last ? 3 : (lev == 1 ? 1 : 2), bytes);
             dispatch_level(W, p, grid, last, st);
             prof_end(ctx, prec);
             // cumulative counts after level lev are the lev-hop degrees
@@ -355,6 +415,9 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
                 hipLaunchKernelGGL(batch_scatter_kernel, dim3((cnt + 255) / 256), dim3(256), 0, st, srcs, first,
                                    cnt, (const uint32_t *)counts, (uint32_t *)nullptr, level_out[lev - 1]);
         }
+        if (row_count && row_count->nrows)
+            hipLaunchKernelGGL(row_count_kernel, dim3((row_count->nrows + 255) / 256 < 4096 ? (row_count->nrows + 255) / 256 : 4096),
+                               dim3(256), 0, st, *row_count, (const uint64_t *)vis, W, first);
         if (te_full) {
             unsigned long long *tep = (unsigned long long *)te;
             hipLaunchKernelGGL(zero_u64_kernel, dim3(1), dim3(256), 0, st, tep, 64 * W);
@@ -397,7 +460,7 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
         be.ncounts = counts_s[parity ^ 1u];
         be.nq = nq;
         be.ncounts_len = 64u * kMaxWidth;
-        const int prec = prof_begin(ctx, 0, 0.0);
+        const int prec = arena ? -1 : prof_begin(ctx, 0, 0.0);
         hipLaunchKernelGGL(batch_end_kernel, dim3(ctx->num_cu * 4), dim3(256), 0, st, be);
         prof_end(ctx, prec);
         first += cnt;
@@ -409,8 +472,28 @@ int msbfs_run(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h
 
 int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                   const uint32_t *srcs, uint32_t nsrc, uint32_t *deg_list, int scatter,
-                  uint32_t *deg_full) {
-    return msbfs_run(ctx, g, alive, h, srcs, nsrc, deg_list, scatter, deg_full, nullptr);
+                  uint32_t *deg_full, Arena *arena, int arena_width) {
+    return msbfs_run(ctx, g, alive, h, srcs, nsrc, deg_list, scatter, deg_full, nullptr, nullptr, arena,
+                     arena_width);
+}
+
+size_t msbfs_arena_bytes(const khc_graph *g, uint32_t h, int W) {
+    size_t sz[B_NUM];
+    msbfs_sizes(g, h + 1, W, false, sz);
+    size_t total = 0;
+    for (int b = 0; b < B_NUM; ++b)
+        if (sz[b]) total = ((total + 255) & ~(size_t)255) + sz[b];
+    return total;
+}
+
+int msbfs_masked_counts(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                        const uint32_t *srcs, uint32_t nsrc, const uint8_t *count_mask, uint32_t *deg_full) {
+    return msbfs_run(ctx, g, alive, h, srcs, nsrc, nullptr, 1, deg_full, nullptr, nullptr, nullptr, 0, count_mask);
+}
+
+int msbfs_row_counts(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h, const uint32_t *srcs,
+                     uint32_t nsrc, const RowCount &rc) {
+    return msbfs_run(ctx, g, alive, h, srcs, nsrc, nullptr, 0, nullptr, nullptr, nullptr, nullptr, 0, nullptr, &rc);
 }
 
 int msbfs_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,

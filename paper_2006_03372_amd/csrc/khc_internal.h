@@ -62,6 +62,7 @@ struct khc_ctx {
     int validate = 1;
     int waves_per_cu = 16;
     uint32_t round_limit = 0;  // 0: peel to the end
+    int push_cost = 0;         // BFS push/pull rule (KHC_OPT_PUSH_COST)
     // workspace
     std::vector<khc::DevBuf> bufs;
     uint64_t ws_bytes = 0;
@@ -91,11 +92,12 @@ struct khc_ctx {
         uint32_t *core, *round;
         uint64_t timeout_ticks;  // barrier deadline baked into the captured launch
         int grouped;             // XCD-grouped (1) or flat (0) barrier
+        uint32_t push_cost;      // push/pull rule baked into the captured launch
         hipGraphExec_t exec;
         bool same_args(const PersistGraph &o) const {
             return g == o.g && h == o.h && W == o.W && grid == o.grid && bounded == o.bounded &&
                    profile == o.profile && round_limit == o.round_limit && core == o.core && round == o.round &&
-                   timeout_ticks == o.timeout_ticks && grouped == o.grouped;
+                   timeout_ticks == o.timeout_ticks && grouped == o.grouped && push_cost == o.push_cost;
         }
     };
     std::vector<PersistGraph> persist_graphs;
@@ -188,15 +190,57 @@ enum WsSlot {
     WS_ITEMS,
     WS_SEG,
     WS_LBX,
+    WS_REGION,
+    WS_ROWCNT,
     WS_NUM_SLOTS
+};
+
+// A device region carved into buffers (256-byte aligned) instead of the
+// context workspace: the entry point that allocates nothing.
+struct Arena {
+    char *base = nullptr;
+    size_t bytes = 0, used = 0;
+    void *take(size_t b) {
+        const size_t at = (used + 255) & ~(size_t)255;
+        if (at > bytes || b > bytes - at) return nullptr;
+        used = at + b;
+        return base + at;
+    }
 };
 
 // Multi-source h-bounded BFS over up to 64*max_width sources per batch;
 // writes deg_out[i] = d^h(srcs[i]) for i < nsrc (device list).  `alive` is
-// a device uint8 mask or null.  Asynchronous.
+// a device uint8 mask or null.  With an arena, every buffer is carved from
+// it (widths up to arena_width, no kernel timing) and nothing is allocated.
+// Asynchronous.
 int msbfs_degrees(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                   const uint32_t *srcs, uint32_t nsrc, uint32_t *deg_out, int scatter,
-                  uint32_t *deg_full);
+                  uint32_t *deg_full, Arena *arena = nullptr, int arena_width = 0);
+// Like msbfs_degrees (scattered by source), but a source's count takes only
+// the reached vertices v with count_mask[v] != 0.
+int msbfs_masked_counts(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                        const uint32_t *srcs, uint32_t nsrc, const uint8_t *count_mask, uint32_t *deg_full);
+// Row counts of the local h-degree update: after a BFS from sources listed
+// by their distance from a removed set (lvl[j] of them at distance j, j =
+// 0..h), acc[u] += the number of sources within h hops of u whose distance
+// from the set is at most h - (mark[u] - 1), for every u in rows.
+struct RowCount {
+    const uint32_t *rows;
+    uint32_t nrows;
+    const uint32_t *mark;
+    const uint32_t *lvl;
+    uint32_t h;
+    uint32_t *acc;
+};
+int msbfs_row_counts(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h, const uint32_t *srcs,
+                     uint32_t nsrc, const RowCount &rc);
+// Bytes msbfs_degrees carves from an arena at width W (alignment included).
+size_t msbfs_arena_bytes(const khc_graph *g, uint32_t h, int W);
+// khdeg_compute after its argument checks; with an arena nothing is
+// allocated (the source list and counter are carved from it as well).
+int khdeg_compute_impl(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h, uint32_t *deg,
+                       Arena *arena, int arena_width);
+
 
 // te_full[s] = arcs a scalar bounded BFS from s examines (live degree summed
 // over the vertices within h-1 hops of s, s included).  Asynchronous.

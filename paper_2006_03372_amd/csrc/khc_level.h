@@ -78,7 +78,10 @@ constexpr int kStageItem = 1024;      // most rows one work item can stage
 
 // Frontier list of one level: every row once (q, count, total degree) and,
 // for rows with more than kPushChunk arcs, one push item per kPushChunk arcs
-// (row | chunk << 32) so heavy rows spread over many wavefronts.
+// (row | chunk << 32) so heavy rows spread over many wavefronts.  qdeg
+// points to two sums over the frontier rows: qdeg[0] = their degrees,
+// qdeg[1] = degree times non-zero words (the (arc, word) pairs a push of
+// the next level would process).
 struct Frontier {
     uint32_t *q;
     uint32_t *qcnt;
@@ -103,7 +106,7 @@ struct LevelParams {
     const uint64_t *hq_in;  // push items of its heavy rows
     const uint32_t *qcnt_in;
     const uint32_t *hcnt_in;
-    const unsigned long long *qdeg_in;
+    const unsigned long long *qdeg_in;  // {degree sum, push pairs} of the previous frontier
     Frontier out;           // this level's frontier
     const uint32_t *q_clr;  // rows of the frontier two levels back
     const uint32_t *qcnt_clr;
@@ -120,6 +123,14 @@ struct LevelParams {
     int count_first;
     uint64_t nnz;  // arcs the pull direction would read (push/pull choice)
     uint32_t n;
+    // push/pull choice: 0 pushes while (frontier degree) * push_factor<W>
+    // < nnz; c > 0 pushes while (push pairs) * c < nnz * W + 4 * rows, the
+    // pull's word gathers plus a per-row share (a push pair is a few
+    // random 8-byte atomics, a pull gather one word of a 16-byte load)
+    uint32_t push_cost;
+    // rows y with count_mask[y] == 0 are reached but not counted (null: all
+    // counted); the sampling mode counts the sampled vertices of a ball
+    const uint8_t *count_mask;
     // pull visits light rows light_rows[light_lo, light_hi) and heavy-row
     // chunks [chunk_lo, chunk_hi) (all of them for one graph; the batch's
     // graphs for graphs packed together)
@@ -265,7 +276,7 @@ static __device__ void flush_staged(const Frontier &f, const uint64_t *row_ptr, 
 // on this level's frontier.  One wavefront, lanes over (arc, word) pairs.
 template <int W, bool LAST>
 __device__ void push_range(const LevelParams &p, uint32_t x, uint64_t ab, uint64_t ae,
-                           uint32_t *s_counts, uint32_t *s_stage, uint32_t *s_sn) {
+                           uint32_t *s_counts, uint32_t *s_stage, uint32_t *s_sn, unsigned long long *s_work) {
     const int lane = threadIdx.x & 63;
     const uint64_t myw = lane < W ? p.frt_in[(size_t)x * W + lane] : 0ull;
     const uint64_t nzmask = __ballot(myw != 0);
@@ -290,10 +301,13 @@ __device__ void push_range(const LevelParams &p, uint32_t x, uint64_t ab, uint64
                     const uint64_t tn =
                         nb & ~(uint64_t)atomicOr((unsigned long long *)vp, (unsigned long long)nb);
                     if (tn) {
-                        count_word_bits(s_counts, w, tn);
-                        if constexpr (!LAST)
-                            atomicOr((unsigned long long *)(p.frt_out + (size_t)y * W + w),
-                                     (unsigned long long)tn);
+                        if (!p.count_mask || p.count_mask[y]) count_word_bits(s_counts, w, tn);
+                        if constexpr (!LAST) {
+                            const uint64_t was = atomicOr((unsigned long long *)(p.frt_out + (size_t)y * W + w),
+                                                          (unsigned long long)tn);
+                            // a word that turns non-zero adds the row's arcs to the next push
+                            if (!was) atomicAdd(s_work, (unsigned long long)(p.row_ptr[y + 1] - p.row_ptr[y]));
+                        }
                         // listed even at the counting level: its vis words
                         // changed, and the batch clears exactly the listed rows
                         const uint32_t ybit = 1u << (y & 31);
@@ -315,7 +329,7 @@ struct LevelLds {
     uint32_t counts[64 * W];
     uint32_t stage[kStage];
     uint32_t sn, base, item, flag;
-    unsigned long long deg;
+    unsigned long long deg, work;
 };
 
 // One level of the multi-source bounded BFS over the whole grid (see the
@@ -333,7 +347,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
     uint32_t *const s_counts = sh.counts;
     uint32_t *const s_stage = sh.stage;
     uint32_t &s_sn = sh.sn, &s_base = sh.base, &s_item = sh.item, &s_flag = sh.flag;
-    unsigned long long &s_deg = sh.deg;
+    unsigned long long &s_deg = sh.deg, &s_work = sh.work;
 
     const int tid = threadIdx.x;
     const int lane = tid & 63;
@@ -356,7 +370,10 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
 
     if (!p.count_keep || p.count_first)
         for (int i = tid; i < 64 * W; i += kBlockThreads) s_counts[i] = 0;
-    if (tid == 0) s_sn = 0;
+    if (tid == 0) {
+        s_sn = 0;
+        s_work = 0;
+    }
     uint64_t pl[WPL][kPlanes];
 #pragma unroll
     for (int j = 0; j < WPL; ++j)
@@ -364,7 +381,9 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
         for (int k = 0; k < kPlanes; ++k) pl[j][k] = 0;
     uint32_t pcount = 0;
 
-    const bool push = (unsigned long long)(*p.qdeg_in) * push_factor<W>() < (unsigned long long)p.nnz;
+    const bool push =
+        p.push_cost ? p.qdeg_in[1] * p.push_cost < (unsigned long long)p.nnz * W + 4ull * (p.light_hi - p.light_lo)
+                    : p.qdeg_in[0] * push_factor<W>() < (unsigned long long)p.nnz;
     const uint32_t qn_in = *p.qcnt_in;
     const uint32_t hn_in = *p.hcnt_in;
     const uint32_t light_grabs = (qn_in + kGrab - 1) / kGrab;
@@ -393,7 +412,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                 if (qi < qn_in) {
                     const uint32_t x = p.q_in[qi];
                     const uint64_t rb = p.row_ptr[x], re = p.row_ptr[x + 1];
-                    if (re - rb <= kPushChunk) push_range<W, LAST>(p, x, rb, re, s_counts, s_stage, &s_sn);
+                    if (re - rb <= kPushChunk) push_range<W, LAST>(p, x, rb, re, s_counts, s_stage, &s_sn, &s_work);
                 }
             } else {
                 const uint32_t hi = (item - light_grabs) * kGrab + wave;
@@ -403,7 +422,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                     const uint64_t rb = p.row_ptr[x], re = p.row_ptr[x + 1];
                     const uint64_t ab = rb + (it >> 32) * kPushChunk;
                     const uint64_t ae = ab + kPushChunk < re ? ab + kPushChunk : re;
-                    push_range<W, LAST>(p, x, ab, ae, s_counts, s_stage, &s_sn);
+                    push_range<W, LAST>(p, x, ab, ae, s_counts, s_stage, &s_sn, &s_work);
                 }
             }
         } else if (item < n_chunk_items) {
@@ -487,7 +506,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                         const uint64_t v = p.vis[(size_t)y * W + tid];
                         nw = s_fin[tid] & ~v;
                         if (nw) {
-                            count_word_bits(s_counts, tid, nw);
+                            if (!p.count_mask || p.count_mask[y]) count_word_bits(s_counts, tid, nw);
                             if constexpr (!LAST) {
                                 p.frt_out[(size_t)y * W + tid] = nw;
                                 p.vis[(size_t)y * W + tid] = v | nw;
@@ -495,8 +514,12 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                         }
                     }
                     if constexpr (!LAST) {
-                        const bool any = __ballot(nw != 0) != 0;
-                        if (tid == 0 && any) atomicOr(&p.fnz_out[y >> 5], 1u << (y & 31));
+                        const uint64_t nzw = __ballot(nw != 0);
+                        const bool any = nzw != 0;
+                        if (tid == 0 && any) {
+                            atomicOr(&p.fnz_out[y >> 5], 1u << (y & 31));
+                            atomicAdd(&s_work, (unsigned long long)(re - rb) * __builtin_popcountll(nzw));
+                        }
                         append_staged(tid == 0 && any, y, s_stage, &s_sn);
                     }
                 }
@@ -600,7 +623,8 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                     nw[j] = acc[j] & ~v[j];
                     any |= nw[j];
                 }
-                planes_add<WPL>(pl, nw);
+                // a row outside the count mask passes its bits on uncounted
+                if (!p.count_mask || !valid || p.count_mask[y]) planes_add<WPL>(pl, nw);
                 if (++pcount == (1u << kPlanes) - 1u) {
                     planes_flush<WPL>(pl, s_counts, lig * WPL);
                     pcount = 0;
@@ -617,7 +641,16 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                     const uint64_t gmask = (LPR == 64) ? ~0ull : ((1ull << LPR) - 1ull);
                     const int gshift = (lane / LPR) * LPR;
                     const bool lead = valid && lig == 0 && ((m >> gshift) & gmask);
-                    if (lead) atomicOr(&p.fnz_out[y >> 5], 1u << (y & 31));
+                    // non-zero words of the row, summed over its lane group
+                    uint32_t nzw = 0;
+#pragma unroll
+                    for (int j = 0; j < WPL; ++j) nzw += nw[j] != 0;
+#pragma unroll
+                    for (int off = LPR / 2; off > 0; off >>= 1) nzw += __shfl_xor(nzw, off, 64);
+                    if (lead) {
+                        atomicOr(&p.fnz_out[y >> 5], 1u << (y & 31));
+                        atomicAdd(&s_work, (unsigned long long)(p.row_ptr[y + 1] - p.row_ptr[y]) * nzw);
+                    }
                     append_staged(lead, y, s_stage, &s_sn);
                 }
             }
@@ -628,6 +661,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
     }
 
     flush_staged(p.out, p.row_ptr, s_stage, &s_sn, &s_base, &s_deg);
+    if (!LAST && tid == 0 && s_work) atomicAdd(p.out.qdeg + 1, s_work);
     planes_flush<WPL>(pl, s_counts, lig * WPL);
     __syncthreads();
     if (!p.count_keep || LAST)

@@ -129,6 +129,41 @@ __global__ void lower_bound_kernel(const uint32_t *list, const uint32_t *s, int 
     }
 }
 
+// Local update (schedule 2): mark (set != 0) or clear the region of the
+// round, the queued vertices (P and every live vertex within h hops of it):
+// pre[v] = 1 on the whole region, post[v] = 1 on it without P; clearing
+// also zeroes the two row counters.
+__global__ void region_kernel(const uint32_t *queue, const uint32_t *s, int h, const uint32_t *mark, uint8_t *pre,
+                              uint8_t *post, uint32_t *cpre, uint32_t *cpost, int set) {
+    uint32_t tot = 0;
+    for (int j = 0; j <= h; ++j) tot += s[R_CNT + j];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gridDim.x * blockDim.x) {
+        const uint32_t v = queue[i];
+        if (set) {
+            pre[v] = 1;
+            post[v] = mark[v] > 1u ? 1 : 0;
+        } else {
+            pre[v] = 0;
+            post[v] = 0;
+            cpre[v] = 0;
+            cpost[v] = 0;
+        }
+    }
+}
+
+// d(u) loses the vertices it reached within h hops before the removal but
+// not after (counted inside the region), for every affected u.
+__global__ void local_apply_kernel(const uint32_t *queue, const uint32_t *s, int h, const uint32_t *cpre,
+                                   const uint32_t *cpost, uint32_t *d) {
+    const uint32_t np = s[R_CNT];
+    uint32_t tot = 0;
+    for (int j = 0; j <= h; ++j) tot += s[R_CNT + j];
+    for (uint32_t i = np + blockIdx.x * blockDim.x + threadIdx.x; i < tot; i += gridDim.x * blockDim.x) {
+        const uint32_t u = queue[i];
+        d[u] -= cpre[u] - cpost[u];
+    }
+}
+
 struct PeelState {
     uint8_t *alive, *dirty;
     uint32_t *d, *dm, *lb, *lbx, *mark, *queue, *list, *s, *part;
@@ -177,6 +212,10 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     const uint32_t n = g->n;
     hipStream_t st = ctx->stream;
     const bool bounded = ctx->schedule == 1 && h >= 2;
+    // schedule 2: each round updates the affected h-degrees inside the
+    // region N^h[P] (Section IV-A's update, for a removed set) when that is
+    // cheaper than recomputing them
+    const bool local = ctx->schedule == 2;
     int rc;
     void *alive_v, *dirty_v, *d_v, *dm_v, *lb_v, *lbx_v, *mark_v, *queue_v, *list_v, *s_v, *part_v, *items_v;
     PeelState p;
@@ -194,6 +233,18 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         (rc = ws_get(ctx, WS_MINPART, (size_t)kMinBlocks * 4, &part_v)) ||
         (rc = ws_get(ctx, WS_ITEMS, round_item_capacity(n, g->nnz) * sizeof(uint2), &items_v)))
         return rc;
+    uint8_t *region_pre = nullptr, *region_post = nullptr;
+    uint32_t *cnt_pre = nullptr, *cnt_post = nullptr;
+    if (local) {
+        void *reg_v, *cnt_v;
+        if ((rc = ws_get(ctx, WS_REGION, (size_t)2 * n + 16, &reg_v)) ||
+            (rc = ws_get(ctx, WS_ROWCNT, (size_t)8 * n + 16, &cnt_v)))
+            return rc;
+        region_pre = (uint8_t *)reg_v;
+        region_post = region_pre + n;
+        cnt_pre = (uint32_t *)cnt_v;
+        cnt_post = cnt_pre + n;
+    }
     p.alive = (uint8_t *)alive_v;
     p.dirty = (uint8_t *)dirty_v;
     p.d = (uint32_t *)d_v;
@@ -259,7 +310,25 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         }
         const uint32_t na = e_h - np;
         if (!bounded) {
-            if (na) {
+            uint32_t e_hm1 = 0;  // P and the vertices within h - 1 hops of it
+            for (uint32_t j = 0; j < h; ++j) e_hm1 += hs[R_CNT + j];
+            if (na && local && 2ull * e_hm1 < na) {
+                // two bounded BFS from the vertices within h-1 hops of P (ordered
+                // by distance), inside the region before and after removal; each
+                // affected u loses what it reached before but not after
+                hipLaunchKernelGGL(region_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, (int)h, p.mark,
+                                   region_pre, region_post, cnt_pre, cnt_post, 1);
+                RowCount rcnt{p.queue + np, na, p.mark, p.s + R_CNT, h, cnt_pre};
+                if ((rc = msbfs_row_counts(ctx, g, region_pre, h, p.queue, e_hm1, rcnt))) return rc;
+                rcnt.acc = cnt_post;
+                if ((rc = msbfs_row_counts(ctx, g, region_post, h, p.queue, e_hm1, rcnt))) return rc;
+                hipLaunchKernelGGL(local_apply_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, (int)h,
+                                   cnt_pre, cnt_post, p.d);
+                hipLaunchKernelGGL(region_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, (int)h, p.mark,
+                                   region_pre, region_post, cnt_pre, cnt_post, 0);
+                st_local.local_rounds += 1;
+                st_local.local_sources += 2ull * e_hm1;
+            } else if (na) {
                 if ((rc = msbfs_degrees(ctx, g, p.alive, h, p.queue + np, na, nullptr, 1, p.d))) return rc;
                 st_local.h_recomputes += na;
             }

@@ -103,6 +103,7 @@ struct PParams {
     uint32_t ngraphs;
     uint32_t h;
     int bounded;
+    uint32_t push_cost;  // push/pull rule of the BFS levels (KHC_OPT_PUSH_COST)
     int profile;  // time the phases (KHC_OPT_PROFILE)
     uint32_t round_limit;  // stop after this many rounds (0: none)
     unsigned long long *progress;  // host-visible [rounds, removed], or null
@@ -665,7 +666,8 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                         p.bwork[i] = 0;
                         p.bqcnt[i] = 0;
                         p.bhcnt[i] = 0;
-                        p.bqdeg[i] = 0;
+                        p.bqdeg[2 * i] = 0;
+                        p.bqdeg[2 * i + 1] = 0;
                     }
                     for (uint32_t i = threadIdx.x; i < per; i += blockDim.x) p.counts[i] = 0;
                     if (threadIdx.x == 0) ctl->stat_batches++;
@@ -706,6 +708,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                     atomicOr(&p.fnz[s >> 5], 1u << (s & 31));
                     const uint64_t ds = p.row_ptr[s + 1] - p.row_ptr[s];
                     atomicAdd(f0.qdeg, (unsigned long long)ds);
+                    atomicAdd(f0.qdeg + 1, (unsigned long long)ds);
                     add_push_items(f0, s, ds);
                 }
                 if (gtid() == 0) *f0.qcnt = cnt;
@@ -728,10 +731,10 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 lp.hq_in = p.bhq + (size_t)(lev - 1) * p.hq_len;
                 lp.qcnt_in = p.bqcnt + lev - 1;
                 lp.hcnt_in = p.bhcnt + lev - 1;
-                lp.qdeg_in = p.bqdeg + lev - 1;
+                lp.qdeg_in = p.bqdeg + 2 * (lev - 1);
                 lp.out.q = p.bq + (size_t)lev * n;
                 lp.out.qcnt = p.bqcnt + lev;
-                lp.out.qdeg = p.bqdeg + lev;
+                lp.out.qdeg = p.bqdeg + 2 * lev;
                 lp.out.hq = p.bhq + (size_t)lev * p.hq_len;
                 lp.out.hcnt = p.bhcnt + lev;
                 lp.q_clr = lev >= 2 ? p.bq + (size_t)(lev - 2) * n : nullptr;
@@ -747,6 +750,8 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 const BatchRange br = *p.brange;
                 lp.nnz = br.arcs;
                 lp.n = n;
+                lp.push_cost = p.push_cost;
+                lp.count_mask = nullptr;
                 lp.light_lo = br.light_lo;
                 lp.light_hi = br.light_hi;
                 lp.chunk_lo = br.chunk_lo;
@@ -909,7 +914,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
         (rc = ws_get(ctx, WS_COUNTS, (size_t)64 * kMaxWidth * 4, &counts)) ||
         (rc = ws_get(ctx, WS_BQUEUE, (size_t)nq * n * 4 + 4, &bq)) ||
         (rc = ws_get(ctx, WS_HQUEUE, (size_t)nq * hq_len * 8, &bhq)) ||
-        (rc = ws_get(ctx, WS_MISC, (size_t)nq * 24 + 64, &bctr)) ||
+        (rc = ws_get(ctx, WS_MISC, (size_t)nq * 32 + 64, &bctr)) ||
         (rc = ws_get(ctx, WS_ALIVE, (size_t)n + 8, &alive)) ||
         (rc = ws_get(ctx, WS_DIRTY, (size_t)n + 8, &dirty)) ||
         (rc = ws_get(ctx, WS_DEG, (size_t)n * 4 + 8, &d)) ||
@@ -932,7 +937,8 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.col = g->col;
     p.nnz = g->nnz;
     p.n = n;
-    p.n_light = g->n_light_nz;  // rows without arcs (a suffix) never gain a bit
+    p.n_light = g->n_light_nz;
+    p.push_cost = (uint32_t)ctx->push_cost;  // rows without arcs (a suffix) never gain a bit
     p.n_chunks = g->n_chunks;
     p.light_rows = g->light_rows;
     p.heavy_rows = g->heavy_rows;
@@ -975,7 +981,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.bhq = (uint64_t *)bhq;
     p.hq_len = hq_len;
     p.bqdeg = (unsigned long long *)bctr;
-    p.bwork = (uint32_t *)(p.bqdeg + nq);
+    p.bwork = (uint32_t *)(p.bqdeg + 2 * nq);
     p.bqcnt = p.bwork + nq;
     p.bhcnt = p.bqcnt + nq;
     p.brange = (BatchRange *)seg;
@@ -1006,7 +1012,8 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
 
     // one graph per argument set, replayed on later calls
     khc_ctx::PersistGraph key{g,           h,         W,       grid, bounded ? 1 : 0, p.profile, p.round_limit,
-                              core,        peel_round, p.sync.timeout_ticks, (int)p.sync.grouped, nullptr};
+                              core,        peel_round, p.sync.timeout_ticks, (int)p.sync.grouped, p.push_cost,
+                              nullptr};
     hipGraphExec_t exec = nullptr;
     for (auto &e : ctx->persist_graphs)
         if (e.same_args(key)) exec = e.exec;

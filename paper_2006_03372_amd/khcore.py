@@ -32,6 +32,7 @@ OPT_DRIVER = 7
 OPT_PERSIST_WIDTH = 8
 OPT_BARRIER_TIMEOUT = 9
 OPT_ROUND_LIMIT = 10
+OPT_PUSH_COST = 11
 
 EXPORTED = [
     "khc_create", "khc_destroy", "khc_last_error", "khc_set_option", "khc_profile_read",
@@ -41,7 +42,7 @@ EXPORTED = [
     "khc_mlp_create", "khc_mlp_destroy", "khc_mlp_set_params", "khc_mlp_get_params",
     "khc_mlp_forward", "khc_mlp_gradient", "khc_mlp_train", "khc_features", "khcore_decompose_approx",
     "khc_persist_profile_read", "khc_set_progress", "khc_autotune", "khc_mlp_save", "khc_mlp_load",
-    "khc_mlp_get_moments",
+    "khc_mlp_get_moments", "khcore_decompose_sampled",
 ]
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32)
@@ -94,7 +95,8 @@ class Stats(ctypes.Structure):
     _fields_ = [("rounds", ctypes.c_uint64), ("h_recomputes", ctypes.c_uint64),
                 ("hm1_recomputes", ctypes.c_uint64), ("bfs_batches", ctypes.c_uint64),
                 ("affected_total", ctypes.c_uint64), ("max_level", ctypes.c_uint32),
-                ("width_words", ctypes.c_uint32), ("wall_ms", ctypes.c_double)]
+                ("width_words", ctypes.c_uint32), ("wall_ms", ctypes.c_double),
+                ("local_rounds", ctypes.c_uint64), ("local_sources", ctypes.c_uint64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -138,6 +140,7 @@ def load_library(path: str = LIB_PATH):
         "khc_mlp_train": ([P, P, P, P, u32, u32, u32, ctypes.c_float, u64, P], i32),
         "khc_features": ([P, P, P, u32, P, P, P], i32),
         "khcore_decompose_approx": ([P, P, u32, P, P, P, ctypes.POINTER(Stats)], i32),
+        "khcore_decompose_sampled": ([P, P, u32, P, P, P, ctypes.POINTER(Stats)], i32),
         "khc_persist_profile_read": ([P, P, P, i32], i32),
         "khc_set_progress": ([P, PROGRESS_FN, P, u32], i32),
         "khc_autotune": ([P, P, u32, u32, ctypes.POINTER(Tune)], i32),
@@ -269,6 +272,17 @@ class Context:
         self._check(self.lib.khcore_decompose_approx(self.handle, graph.handle, h,
                                                      None if mlp is None else mlp.handle, _dptr(core),
                                                      _dptr(est), ctypes.byref(st)))
+        return core, est, st.as_dict()
+
+    def core_sampled(self, graph: "Graph", h: int, sampled, with_estimate: bool = False):
+        """Sampling-based approximate core numbers on the vertex sample
+        `sampled` (device uint8 mask): (core, estimate or None, stats)."""
+        torch = _torch()
+        core = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+        est = torch.empty(graph.n, dtype=torch.int32, device=graph.device) if with_estimate else None
+        st = Stats()
+        self._check(self.lib.khcore_decompose_sampled(self.handle, graph.handle, h, _dptr(sampled), _dptr(core),
+                                                      _dptr(est), ctypes.byref(st)))
         return core, est, st.as_dict()
 
     def validate(self, row_ptr, col, n: int) -> int:

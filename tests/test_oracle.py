@@ -307,3 +307,108 @@ def test_generators_deterministic_and_simple(oracle_lib):
     assert (c1.col == c2.col).all()
     assert oracle.check_csr(c1) == 0
     assert 3.0 < c1.nnz / c1.n / 1.0 < 12.0
+
+
+# ---------------------------------------------------------------- sampling
+
+def test_sampled_peel_with_every_vertex_sampled_is_exact():
+    """With S = V the sampled count is the h-degree and the rate is 1, so
+    the sampling-based peel gives the exact core numbers."""
+    for g, h in ((synth.chung_lu(300, 6.0, 2.5, seed=3), 2), (synth.rmat(8, 8, seed=2), 3),
+                 (synth.petersen(), 2), (synth.cycle(11), 2)):
+        c, est = oracle.peel_sampled(g, h, np.ones(g.n, np.uint8))
+        assert (c == oracle.peel(g, h)[0]).all()
+
+
+@settings(max_examples=25, deadline=None)
+@given(st.integers(5, 9), st.floats(0.2, 0.7), st.integers(0, 10 ** 6), st.integers(1, 3), st.floats(0.2, 0.8))
+def test_sampled_peel_matches_brute_force(n, p, seed, h, rate):
+    g = synth.erdos_renyi(n, p, seed)
+    sampled = (np.random.default_rng(seed + 1).random(n) < rate).astype(np.uint8)
+    c, _ = oracle.peel_sampled(g, h, sampled)
+    ref = R.brute_core_sampled(g.n, g.row_ptr, g.col, h, sampled)
+    assert (c == ref).all(), (c, ref)
+
+
+def test_sampled_estimate_never_grows_and_starts_exact():
+    """The estimate at removal is at most the initial h-degree (sel <= sel0),
+    and a vertex removed in the first round keeps its exact degree."""
+    g = synth.chung_lu(800, 8.0, 2.5, seed=9)
+    sampled = (np.random.default_rng(4).random(g.n) < 0.2).astype(np.uint8)
+    c, est = oracle.peel_sampled(g, 2, sampled)
+    d0 = oracle.hdeg(g, 2)
+    assert (est <= d0).all()
+    first = c == c.min()
+    assert (est[first & (c == d0.min())] == d0[first & (c == d0.min())]).all()
+
+
+# ------------------------------------------------ local h-degree update
+
+def test_table2_bitmaps():
+    """Table 2 / Example 3: relabelling, region edges and every bitmap row."""
+    g, _ = _golden()
+    rows = {ln.split()[0] + ("" if ln.split()[0] != "bitmaps" else " " + ln.split()[1]): ln.split()[1:]
+            for ln in open(os.path.join(GOLDEN, "table2_bitmaps.txt")) if ln.strip() and not ln.startswith("#")}
+    alive = np.ones(14, dtype=np.uint8)
+    for x in rows["remove"]:
+        alive[int(x) - 1] = 0
+    v, h = int(rows["vertex"][0]) - 1, int(rows["h"][0])
+    labels, edges, hist, new = R.bitmap_update(g.n, g.row_ptr, g.col, alive, h, v)
+    assert [u + 1 for u in labels] == [int(x) for x in rows["relabel"]]
+    assert edges == sorted(tuple(int(a) for a in e.split("-")) for e in rows["region_edges"])
+    assert hist[0] == [int(x) for x in rows["bitmaps init"][1:]]
+    assert hist[1] == [int(x) for x in rows["bitmaps iter1"][1:]]
+    assert hist[2] == [int(x) for x in rows["bitmaps iter2"][1:]]
+    # and the updated degrees are the recomputed ones (Observation 2)
+    after = alive.copy()
+    after[v] = 0
+    d = oracle.hdeg(g, h, after)
+    assert all(d[u] == k for u, k in new.items())
+
+
+def test_example2_by_bitmap_update():
+    """Example 2: deleting v1 (h = 2) leaves v2, v3, v4, v6 with 2-hop
+    degrees 3, 3, 7, 7."""
+    g, _ = _golden()
+    _, _, _, new = R.bitmap_update(g.n, g.row_ptr, g.col, np.ones(14, np.uint8), 2, 0)
+    assert {u + 1: k for u, k in new.items()} == {2: 3, 3: 3, 4: 7, 6: 7}
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(6, 30), st.floats(0.08, 0.5), st.integers(0, 10 ** 6), st.integers(1, 4))
+def test_bitmap_update_equals_recompute(n, p, seed, h):
+    """Theorem 1 / Observation 2: the update inside the ball equals the
+    h-degrees recomputed on the whole graph without v."""
+    g = synth.erdos_renyi(n, p, seed)
+    rng = np.random.default_rng(seed)
+    alive = (rng.random(n) < 0.85).astype(np.uint8)
+    live = np.flatnonzero(alive)
+    if live.size == 0:
+        return
+    v = int(rng.choice(live))
+    _, _, _, new = R.bitmap_update(g.n, g.row_ptr, g.col, alive, h, v)
+    after = alive.copy()
+    after[v] = 0
+    d = oracle.hdeg(g, h, after)
+    assert all(d[u] == k for u, k in new.items())
+
+
+@settings(max_examples=40, deadline=None)
+@given(st.integers(6, 30), st.floats(0.08, 0.5), st.integers(0, 10 ** 6), st.integers(1, 4), st.integers(1, 5))
+def test_set_local_update_equals_recompute(n, p, seed, h, k):
+    """The set form: removing several vertices at once, the region-only
+    update equals the recomputed h-degrees of every affected vertex."""
+    g = synth.erdos_renyi(n, p, seed)
+    rng = np.random.default_rng(seed + 7)
+    alive = (rng.random(n) < 0.9).astype(np.uint8)
+    live = np.flatnonzero(alive)
+    if live.size == 0:
+        return
+    P = rng.choice(live, size=min(k, live.size), replace=False)
+    new = R.set_local_update(g.n, g.row_ptr, g.col, alive, h, P)
+    after = alive.copy()
+    after[P] = 0
+    d = oracle.hdeg(g, h, after)
+    assert all(d[u] == k2 for u, k2 in new.items())
+    # a dropped term (the pre-removal reach test) would count vertices that
+    # were never within h hops: on some case the plain difference differs
