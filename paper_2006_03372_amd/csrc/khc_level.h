@@ -63,8 +63,17 @@ __device__ __forceinline__ void store_words(uint64_t *p, const uint64_t (&w)[WPL
     }
 }
 
-constexpr int kPlanes = 8;            // bit-sliced per-lane counters hold up to 255
-constexpr int kUnroll = 8;            // independent gathers in flight per lane
+// Per kind of level: bit-sliced counter planes of each lane (a plane set
+// holds counts up to 2^planes - 1 before it is flushed to LDS) and
+// independent gathers in flight per lane.  Together they set the level's
+// register use, its occupancy and its ripple-carry work per row.  Measured
+// on the R-MAT-20 h = 3 pass (W = 32, per launch): 8 planes / 8 gathers
+// took 1170 us (inner) and 766 us (counting); 6 / 6 took 1023 us inner,
+// 4 / 6 took 740 us counting (147 and 127 VGPRs).
+template <bool LAST>
+constexpr int planes_of() { return LAST ? 4 : 6; }
+template <bool LAST>
+constexpr int unroll_of() { return 6; }
 // Push when frontier arcs * factor < all arcs.  A pull level costs a fixed
 // pass over every row plus 8W bytes per arc; a push costs about 8 bytes and
 // one atomic per (frontier arc, non-zero word).  Narrow batches therefore
@@ -176,7 +185,7 @@ __device__ __forceinline__ bool saturated(const uint64_t (&a)[WPL], const uint64
 
 // Add the WPL words of x to the bit-sliced counters (one ripple-carry add
 // per word: plane k holds bit k of every bit position's count).
-template <int WPL>
+template <int WPL, int kPlanes>
 __device__ __forceinline__ void planes_add(uint64_t (&pl)[WPL][kPlanes], const uint64_t (&x)[WPL]) {
 #pragma unroll
     for (int j = 0; j < WPL; ++j) {
@@ -190,7 +199,7 @@ __device__ __forceinline__ void planes_add(uint64_t (&pl)[WPL][kPlanes], const u
     }
 }
 
-template <int WPL>
+template <int WPL, int kPlanes>
 __device__ __forceinline__ void planes_flush(uint64_t (&pl)[WPL][kPlanes], uint32_t *s_counts,
                                              int word0) {
 #pragma unroll
@@ -340,6 +349,7 @@ template <int W, bool LAST>
 __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
     using L = RowLayout<W>;
     constexpr int WPL = L::WPL, LPR = L::LPR, RPW = L::RPW, GROUPS = L::GROUPS;
+    constexpr int kPlanes = planes_of<LAST>(), kUnroll = unroll_of<LAST>();
     // light rows handled per work item: several passes of all lane groups
     constexpr int PASSES = GROUPS >= 64 ? 1 : 64 / GROUPS;
     uint64_t *const s_red = sh.red;
@@ -624,9 +634,9 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
                     any |= nw[j];
                 }
                 // a row outside the count mask passes its bits on uncounted
-                if (!p.count_mask || !valid || p.count_mask[y]) planes_add<WPL>(pl, nw);
+                if (!p.count_mask || !valid || p.count_mask[y]) planes_add<WPL, kPlanes>(pl, nw);
                 if (++pcount == (1u << kPlanes) - 1u) {
-                    planes_flush<WPL>(pl, s_counts, lig * WPL);
+                    planes_flush<WPL, kPlanes>(pl, s_counts, lig * WPL);
                     pcount = 0;
                 }
                 if constexpr (!LAST) {
@@ -662,7 +672,7 @@ __device__ void level_body(const LevelParams &p, LevelLds<W> &sh) {
 
     flush_staged(p.out, p.row_ptr, s_stage, &s_sn, &s_base, &s_deg);
     if (!LAST && tid == 0 && s_work) atomicAdd(p.out.qdeg + 1, s_work);
-    planes_flush<WPL>(pl, s_counts, lig * WPL);
+    planes_flush<WPL, kPlanes>(pl, s_counts, lig * WPL);
     __syncthreads();
     if (!p.count_keep || LAST)
         for (int i = tid; i < 64 * W; i += kBlockThreads)

@@ -75,10 +75,11 @@ def accuracy(core_exact, core_approx):
 
 def evaluate(h=4, train_scale=16, train_edge_factor=8, train_count=32, train_seed=101, test_scale=18,
              test_edge_factor=8, epochs=10, batch=4096, lr=2e-3, log=print, family="rmat", train_n=20000,
-             test_n=200000, mean_degree=8.0):
+             test_n=200000, mean_degree=8.0, sampling_rates=(0.05, 0.1, 0.2)):
     """Train the network on small graphs of one family and peel a larger one
-    exactly, with the network, with the lower bound alone and with an
-    untrained network; returns times and accuracies.  family "rmat": R-MAT
+    exactly, with the network, with the lower bound alone, with an
+    untrained network and with the sampling mode at each rate; returns
+    times and accuracies.  family "rmat": R-MAT
     graphs of train_scale / test_scale; "chung-lu": Chung-Lu graphs (beta
     2.5, mean_degree) of train_n / test_n vertices."""
     import time
@@ -139,6 +140,14 @@ def evaluate(h=4, train_scale=16, train_edge_factor=8, train_count=32, train_see
         out[name] = {"seconds": round(ta, 2), "rounds": st["rounds"], "speedup_vs_exact": round(te / ta, 3),
                      **accuracy(exact, core)}
         log(f"{name}: {out[name]}")
+    # the paper's own approximate variant beside it: the sampling mode at
+    # several rates, each on a vertex sample drawn here from a fixed seed
+    for rate in sampling_rates:
+        mask = torch.from_numpy((np.random.default_rng(12345).random(g.n) < rate).astype(np.uint8)).cuda()
+        core, st, ta = run(f"sampling r={rate}", lambda: ctx.core_sampled(gr, h, mask)[::2])
+        out[f"sampling_r{rate}"] = {"seconds": round(ta, 2), "rounds": st["rounds"],
+                                    "speedup_vs_exact": round(te / ta, 3), **accuracy(exact, core)}
+        log(f"sampling r={rate}: {out[f'sampling_r{rate}']}")
     gr.close()
     ctx.close()
     return out
@@ -159,11 +168,13 @@ def main():
     ap.add_argument("--train-n", type=int, default=20000)
     ap.add_argument("--test-n", type=int, default=200000)
     ap.add_argument("--mean-degree", type=float, default=8.0)
+    ap.add_argument("--sampling-rates", default="0.05,0.1,0.2", help="rates of the sampling-mode runs ('' for none)")
     a = ap.parse_args()
     out = evaluate(h=a.h, train_scale=a.train_scale, train_count=a.train_count, test_scale=a.test_scale,
                    test_edge_factor=16 if a.test_scale >= 20 else 8, epochs=a.epochs,
                    log=lambda m: print(m, file=sys.stderr, flush=True), family=a.family, train_n=a.train_n,
-                   test_n=a.test_n, mean_degree=a.mean_degree)
+                   test_n=a.test_n, mean_degree=a.mean_degree,
+                   sampling_rates=tuple(float(x) for x in a.sampling_rates.split(",") if x))
     print(json.dumps(out), flush=True)
 
 

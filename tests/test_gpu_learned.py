@@ -204,7 +204,13 @@ def test_learned_mode_beats_bounds_only(ctx, h):
     print("learned", acc_l, "bounds only", acc_b, flush=True)
     assert losses[-1] < 0.05 * losses[0]
     assert acc_l["exact_fraction"] >= acc_b["exact_fraction"]
-    assert acc_l["mae"] < 0.85 * acc_b["mae"]
+    # The gain depends on how loose the exact bounds are.  At h = 2 they are
+    # loose and the network cuts the bound-only MAE to about an eighth
+    # (measured 0.67 against 5.4); at h = 4 four hops reach most of these
+    # graphs, the lower bound is nearly tight and the network's gain is
+    # small (measured 8.88 against 11.11, a ratio of 0.80).  Each margin
+    # keeps headroom above its measured ratio.
+    assert acc_l["mae"] < {2: 0.3, 4: 0.9}[h] * acc_b["mae"]
     assert acc_l["precision"] > acc_b["precision"]
     net.close()
 
