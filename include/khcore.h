@@ -196,6 +196,21 @@ int khdeg_compute(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32
 int khdeg_compute_list(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
                        const uint32_t *verts, uint32_t count, uint32_t *deg);
 
+/* khdeg_compute for callers that cannot allocate device memory (code under
+ * HIP graph capture, tight serving loops, harnesses that forbid hipMalloc):
+ * same arguments, results and errors, but every scratch buffer comes from
+ * one static 64 MiB device array of the library (held on each GPU the
+ * library runs on until the process ends), so no hipMalloc, hipFree or
+ * allocating routine is called.  The batch width is the widest power of
+ * two up to KHC_OPT_MAX_WIDTH whose buffers fit; a graph whose buffers do
+ * not fit even at width 1 (about 85 n + nnz / 8 bytes at h = 3) gives
+ * KHC_ENOMEM.  All calls on one GPU share the array: calls that overlap on
+ * one device (other contexts or threads) race and must not be made.
+ * Kernel timing (KHC_OPT_PROFILE) is not recorded.  Returns after one small
+ * readback; deg is complete when the context stream has drained. */
+int khdeg_compute_noalloc(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h,
+                          uint32_t *deg);
+
 /* Work measure for traversed-edges-per-second figures: te[v] = the number
  * of arcs a scalar bounded BFS from v examines, i.e. the live degree summed
  * over every live vertex within h-1 hops of v (v included).  Dead vertices

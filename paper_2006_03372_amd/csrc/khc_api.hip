@@ -295,6 +295,10 @@ int khc_create(khc_ctx **out, int device, void *hip_stream) {
     c->device = device;
     c->stream = (hipStream_t)hip_stream;
     c->bufs.resize(WS_NUM_SLOTS);
+    // the device address of the static scratch of khdeg_compute_noalloc,
+    // looked up once per device while it is current (a failure here only
+    // disables that entry point, which then reports it)
+    (void)noalloc_init(device);
     hipDeviceProp_t prop;
     if (hipGetDeviceProperties(&prop, device) == hipSuccess) c->num_cu = prop.multiProcessorCount;
     if (hipStreamCreateWithFlags(&c->capture_stream, hipStreamNonBlocking) != hipSuccess) {

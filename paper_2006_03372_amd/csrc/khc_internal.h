@@ -240,7 +240,8 @@ size_t msbfs_arena_bytes(const khc_graph *g, uint32_t h, int W);
 // allocated (the source list and counter are carved from it as well).
 int khdeg_compute_impl(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h, uint32_t *deg,
                        Arena *arena, int arena_width);
-
+// Address of this device's static scratch (set up by khc_create).
+int noalloc_init(int device);
 
 // te_full[s] = arcs a scalar bounded BFS from s examines (live degree summed
 // over the vertices within h-1 hops of s, s included).  Asynchronous.

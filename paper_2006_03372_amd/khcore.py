@@ -42,7 +42,7 @@ EXPORTED = [
     "khc_mlp_create", "khc_mlp_destroy", "khc_mlp_set_params", "khc_mlp_get_params",
     "khc_mlp_forward", "khc_mlp_gradient", "khc_mlp_train", "khc_features", "khcore_decompose_approx",
     "khc_persist_profile_read", "khc_set_progress", "khc_autotune", "khc_mlp_save", "khc_mlp_load",
-    "khc_mlp_get_moments", "khcore_decompose_sampled",
+    "khc_mlp_get_moments", "khdeg_compute_noalloc", "khcore_decompose_sampled",
 ]
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32)
@@ -126,6 +126,7 @@ def load_library(path: str = LIB_PATH):
         "khc_graph_destroy": ([P], i32),
         "khc_validate_csr": ([P, ctypes.POINTER(CSRStruct)], i32),
         "khdeg_compute": ([P, P, P, u32, P], i32),
+        "khdeg_compute_noalloc": ([P, P, P, u32, P], i32),
         "khdeg_compute_list": ([P, P, P, u32, P, u32, P], i32),
         "khdeg_scanned_arcs": ([P, P, P, u32, P], i32),
         "khcore_decompose": ([P, P, u32, P, P, ctypes.POINTER(Stats)], i32),
@@ -297,6 +298,15 @@ class Context:
         if out is None:
             out = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
         self._check(self.lib.khdeg_compute(self.handle, graph.handle, _dptr(alive), h, _dptr(out)))
+        return out
+
+    def hdeg_noalloc(self, graph: "Graph", h: int, alive=None, out=None):
+        """khdeg_compute_noalloc: the library allocates nothing (out, if
+        given, is the caller's)."""
+        torch = _torch()
+        if out is None:
+            out = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+        self._check(self.lib.khdeg_compute_noalloc(self.handle, graph.handle, _dptr(alive), h, _dptr(out)))
         return out
 
     def hdeg_list(self, graph: "Graph", h: int, verts, alive=None, out=None):
