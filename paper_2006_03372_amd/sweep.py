@@ -11,6 +11,10 @@ the time budget, one exact decomposition (host-driven rounds, bounded
 schedule).  Every run prints one JSON line.
 
     python -m paper_2006_03372_amd.sweep --rmat 16,18,20,22 --chung-lu 100000,400000 --h 2,3
+
+With --schedules it instead times one exact decomposition per schedule
+(KHC_OPT_SCHEDULE 1 bounded, 2 local update, 0 plain; plain at h = 2 only)
+of every graph and h, and checks that all schedules give the same cores.
 """
 from __future__ import annotations
 
@@ -55,11 +59,36 @@ def measure(ctx, g, desc, h, steps, decompose):
     return out
 
 
+def schedules(ctx, g, desc, h):
+    import torch
+    from . import khcore
+    gr = ctx.graph(g)
+    ref = None
+    for sched in (1, 2, 0):
+        if sched == 0 and h >= 3:
+            continue
+        ctx.set_option(khcore.OPT_SCHEDULE, sched)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        core, _, st = ctx.core(gr, h)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        c = core.cpu().numpy()
+        ref = c if ref is None else ref
+        print(json.dumps({"graph": desc, "h": h, "schedule": sched, "s": round(t, 3), "rounds": st["rounds"],
+                          "local_rounds": st["local_rounds"], "h_recomputes": st["h_recomputes"],
+                          "same": bool((c == ref).all())}), flush=True)
+    ctx.set_option(khcore.OPT_SCHEDULE, 1)
+    gr.close()
+
+
 def main():
     from . import khcore, synth
     ap = argparse.ArgumentParser(description=__doc__.splitlines()[0])
     ap.add_argument("--rmat", default="16,18,20", help="R-MAT scales")
     ap.add_argument("--chung-lu", default="", help="Chung-Lu sizes")
+    ap.add_argument("--chung-lu-mean", type=float, default=10.0)
+    ap.add_argument("--schedules", action="store_true", help="time the decomposition schedules instead")
     ap.add_argument("--h", default="2,3")
     ap.add_argument("--steps", type=int, default=3)
     ap.add_argument("--decompose-max", type=int, default=400000,
@@ -72,13 +101,17 @@ def main():
         ef = 16 if sc >= 20 else 8
         graphs.append((lambda sc=sc, ef=ef: synth.rmat(sc, ef, seed=1), f"R-MAT scale {sc} ef {ef}"))
     for n in [int(x) for x in a.chung_lu.split(",") if x]:
-        graphs.append((lambda n=n: synth.chung_lu(n, 10.0, 2.5, seed=1), f"Chung-Lu n={n} mean 10"))
+        m = a.chung_lu_mean
+        graphs.append((lambda n=n, m=m: synth.chung_lu(n, m, 2.5, seed=1), f"Chung-Lu n={n} mean {m:g}"))
     for make, desc in graphs:
         t0 = time.time()
         g = make()
         live = int(np.count_nonzero(g.degrees()))
         _log(f"{desc}: n={g.n} edges={g.num_edges} ({time.time() - t0:.1f} s)")
         for h in [int(x) for x in a.h.split(",")]:
+            if a.schedules:
+                schedules(ctx, g, desc, h)
+                continue
             limit = a.decompose_max if h <= 2 else a.decompose_max // 4
             res = measure(ctx, g, desc, h, a.steps, live <= limit)
             print(json.dumps(res), flush=True)
