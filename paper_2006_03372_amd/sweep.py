@@ -33,21 +33,22 @@ def _log(msg):
 def measure(ctx, g, desc, h, steps, decompose):
     import torch
     gr = ctx.graph(g)
-    te = ctx.scanned_arcs(gr, h)
-    torch.cuda.synchronize()
-    te_total = int(te.cpu().numpy().view(np.uint64).sum())
-    del te
-    ctx.hdeg(gr, h)
-    torch.cuda.synchronize()
-    times = []
-    for _ in range(steps):
-        t0 = time.perf_counter()
+    out = {"graph": desc, "n": g.n, "edges": g.num_edges, "h": h}
+    if steps > 0:
+        te = ctx.scanned_arcs(gr, h)
+        torch.cuda.synchronize()
+        te_total = int(te.cpu().numpy().view(np.uint64).sum())
+        del te
         ctx.hdeg(gr, h)
         torch.cuda.synchronize()
-        times.append(time.perf_counter() - t0)
-    t = float(np.median(times))
-    out = {"graph": desc, "n": g.n, "edges": g.num_edges, "h": h, "hdeg_ms": round(t * 1e3, 2),
-           "traversed_edges": te_total, "gteps": round(te_total / t / 1e9, 1)}
+        times = []
+        for _ in range(steps):
+            t0 = time.perf_counter()
+            ctx.hdeg(gr, h)
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        t = float(np.median(times))
+        out.update({"hdeg_ms": round(t * 1e3, 2), "traversed_edges": te_total, "gteps": round(te_total / t / 1e9, 1)})
     if decompose:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -90,7 +91,7 @@ def main():
     ap.add_argument("--chung-lu-mean", type=float, default=10.0)
     ap.add_argument("--schedules", action="store_true", help="time the decomposition schedules instead")
     ap.add_argument("--h", default="2,3")
-    ap.add_argument("--steps", type=int, default=3)
+    ap.add_argument("--steps", type=int, default=3, help="timed khdeg_compute runs (0: decomposition only)")
     ap.add_argument("--decompose-max", type=int, default=400000,
                     help="decompose graphs with at most this many non-isolated vertices (h=2) "
                          "or a quarter of it (h>=3)")
