@@ -234,11 +234,22 @@ def calibrate(kind, mib):
     idx = torch.randint(0, rows, (rows,), dtype=torch.int64, device="cuda",
                         generator=torch.Generator(device="cuda").manual_seed(1))
     out = torch.empty_like(table)
+    ms = []
     for _ in range(3):
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record()
         torch.index_select(table, 0, idx, out=out)
+        b.record()
+        b.synchronize()
+        ms.append(a.elapsed_time(b))
     torch.cuda.synchronize()
+    moved = rows * (256 + 8) + rows * 256
+    # the rate of this access pattern on this GPU (random 256-byte rows read
+    # with 16-byte loads, rows written in order), a practical ceiling beside
+    # the HBM peak for the BFS level's gathers
     print(json.dumps({"calibration": "gather", "rows": rows, "bytes_read": rows * (256 + 8),
-                      "bytes_written": rows * 256, "runs": 3}))
+                      "bytes_written": rows * 256, "runs": 3, "ms": [round(x, 3) for x in ms],
+                      "GBs_best": round(moved / (min(ms) * 1e-3) / 1e9, 1)}))
 
 
 def main():

@@ -68,6 +68,7 @@ typedef struct {
     double wall_ms;           /* host wall time of the call                     */
     uint64_t local_rounds;    /* rounds that updated h-degrees locally (schedule 2) */
     uint64_t local_sources;   /* BFS sources of those local updates             */
+    uint64_t gate_deferrals;  /* recomputes the learned gate deferred           */
 } khc_stats;
 
 /* ---- context ---------------------------------------------------------- */
@@ -261,9 +262,13 @@ int khcore_decompose_batched(khc_ctx *ctx, uint32_t G, const uint64_t *vtx_base,
  * sampled vertices within h hops in the current graph; its estimated
  * h-degree is floor(sel * d0 / sel0), i.e. sel divided by the initial rate
  * sel0 / d0 (d0 when sel0 = 0).  Peeling runs on the estimate as
- * khcore_decompose runs on the h-degree, recounting sel for the live
- * vertices within h hops of each round's removed set.  The estimate never
- * grows under removal, so the result does not depend on the removal order.
+ * khcore_decompose runs on the h-degree.  After each round only vertices
+ * that can lose a sampled vertex recount sel: a vertex at distance j from
+ * the removed set P can only lose vertices within h - j hops of P, so with
+ * r0 the distance from P of the nearest sampled vertex the live vertices
+ * within h - r0 hops of P recount, and none when no sampled vertex lies
+ * within h - 1 hops.  The estimate never grows under removal, so the
+ * result does not depend on the removal order.
  *   sampled   device uint8[n]: nonzero marks a sampled vertex
  *   h         1..1024
  *   core      device uint32[n] output: the approximate core numbers
@@ -359,6 +364,36 @@ int khc_features(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_
  * estimate when it was removed.  2 <= h <= 64.  Synchronous. */
 int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const khc_mlp *mlp,
                             uint32_t *core, uint32_t *estimate, khc_stats *stats);
+
+/* Features of the learned recompute gate for every vertex of G(alive):
+ * X device float[n][8], each log1p(count) / 8 of: the live degree of v,
+ * dm(v), min, mean and max over live neighbours w of dm(w), the mean full
+ * degree of the live neighbours, min(live - 1, sum over live w of dm(w)),
+ * live - 1.  dm (device uint32[n]) holds (h-1)-degrees or lower bounds on
+ * them (khdeg_compute at h - 1 gives the exact ones); the network is
+ * trained to predict log1p(d^h(v)) / 8 from them.  Dead vertices get
+ * zeros.  2 <= h <= 1024.  Asynchronous. */
+int khc_gate_features(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h, const uint32_t *dm,
+                      float *X);
+
+/* Gated (k,h)-core decomposition: the bounded schedule of khcore_decompose
+ * (host-driven rounds, Algorithms 1-2 in level-synchronous form) with a
+ * learned gate in front of its recomputes.  A dirty vertex whose exact
+ * lower bound lb reached the level k (its stale h-degree d still above k)
+ * is first estimated: e = clamp(expm1(8 y), lb, d) with y the network's
+ * output on khc_gate_features; if lb + floor((e - lb) * (1 - margin)) > k
+ * that value becomes its key and the recompute is deferred until the level
+ * reaches it or a later removal affects the vertex.  Vertices still leave
+ * only with an exact or stale h-degree <= k, so every returned core number
+ * is at least the exact one.  mlp == NULL or margin == 1 defers nothing and
+ * gives the exact core numbers and removal rounds of khcore_decompose.
+ *   margin      0..1
+ *   core        device uint32[n] output
+ *   peel_round  device uint32[n] or NULL
+ *   stats       host or NULL (gate_deferrals counts the deferrals)
+ * 2 <= h <= 1024, one graph.  Synchronous. */
+int khcore_decompose_gated(khc_ctx *ctx, const khc_graph *g, uint32_t h, const khc_mlp *mlp, float margin,
+                           uint32_t *core, uint32_t *peel_round, khc_stats *stats);
 
 #ifdef __cplusplus
 }

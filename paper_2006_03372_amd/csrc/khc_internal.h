@@ -192,6 +192,7 @@ enum WsSlot {
     WS_LBX,
     WS_REGION,
     WS_ROWCNT,
+    WS_GATE_LIST,
     WS_NUM_SLOTS
 };
 
@@ -261,9 +262,18 @@ void fill_u32(khc_ctx *ctx, uint32_t *p, uint32_t value, uint64_t count);
 // Whole decomposition in one persistent kernel (khc_persist.hip).
 int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,
                          uint32_t *peel_round, khc_stats *stats);
-// Host-driven decomposition (khc_peel.hip).
+// Learned recompute gate of the bounded schedule (khc_gate.hip).
+struct GateArgs {
+    const khc_mlp *mlp;  // null: no gate
+    float margin;        // 0..1: soft key = lb + (estimate - lb) * (1 - margin)
+};
+int gate_pass(khc_ctx *ctx, const khc_graph *g, const khc_mlp *mlp, float margin, const uint8_t *alive,
+              const uint32_t *dm, const uint32_t *list, uint32_t rn, uint32_t *lb, const uint32_t *d, uint8_t *dirty,
+              const uint32_t *part, uint32_t *s, float *X, float *Y, uint32_t *out);
+// Host-driven decomposition (khc_peel.hip); a non-null gate forces the
+// bounded schedule and puts the learned gate in front of its recomputes.
 int host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core, uint32_t *peel_round,
-                   khc_stats *stats);
+                   khc_stats *stats, const GateArgs *gate = nullptr);
 // Calls the progress callback when its interval has passed since *last.
 void report_progress(khc_ctx *ctx, std::chrono::steady_clock::time_point *last, uint32_t rounds, uint64_t removed,
                      uint32_t level);

@@ -201,7 +201,7 @@ int peel_round_common(khc_ctx *ctx, const khc_graph *g, uint32_t h, const PeelSt
 using namespace khc;
 
 int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *core,
-                        uint32_t *peel_round, khc_stats *stats) {
+                        uint32_t *peel_round, khc_stats *stats, const GateArgs *gate) {
     if (g->ngraphs > 1)
         return set_error(ctx, KHC_EINVAL, "graphs packed together need the persistent driver");
     if (h > kMaxRoundH) return set_error(ctx, KHC_EINVAL, "h above 1024");
@@ -211,11 +211,12 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     std::memset(&st_local, 0, sizeof(st_local));
     const uint32_t n = g->n;
     hipStream_t st = ctx->stream;
-    const bool bounded = ctx->schedule == 1 && h >= 2;
+    const bool gated = gate && gate->mlp && h >= 2;
+    const bool bounded = (ctx->schedule == 1 || gated) && h >= 2;
     // schedule 2: each round updates the affected h-degrees inside the
     // region N^h[P] (Section IV-A's update, for a removed set) when that is
     // cheaper than recomputing them
-    const bool local = ctx->schedule == 2;
+    const bool local = ctx->schedule == 2 && !gated;
     int rc;
     void *alive_v, *dirty_v, *d_v, *dm_v, *lb_v, *lbx_v, *mark_v, *queue_v, *list_v, *s_v, *part_v, *items_v;
     PeelState p;
@@ -233,6 +234,18 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         (rc = ws_get(ctx, WS_MINPART, (size_t)kMinBlocks * 4, &part_v)) ||
         (rc = ws_get(ctx, WS_ITEMS, round_item_capacity(n, g->nnz) * sizeof(uint2), &items_v)))
         return rc;
+    float *gate_x = nullptr, *gate_y = nullptr;
+    uint32_t *gate_list = nullptr;
+    if (gated) {
+        void *x_v, *y_v, *l_v;
+        if ((rc = ws_get(ctx, WS_APPROX_X, (size_t)n * 8 * 4 + 32, &x_v)) ||
+            (rc = ws_get(ctx, WS_APPROX_Y, (size_t)n * 4 + 8, &y_v)) ||
+            (rc = ws_get(ctx, WS_GATE_LIST, (size_t)n * 4 + 8, &l_v)))
+            return rc;
+        gate_x = (float *)x_v;
+        gate_y = (float *)y_v;
+        gate_list = (uint32_t *)l_v;
+    }
     uint8_t *region_pre = nullptr, *region_post = nullptr;
     uint32_t *cnt_pre = nullptr, *cnt_post = nullptr;
     if (local) {
@@ -296,10 +309,25 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
             if (e != hipSuccess) return check_hip(ctx, e, "level readback");
             const uint32_t rn = hs[R_RN];
             if (rn == 0) break;
-            if ((rc = msbfs_degrees(ctx, g, p.alive, h, p.list, rn, nullptr, 1, p.d))) return rc;
-            hipLaunchKernelGGL(set_flag_kernel, dim3(grid_n), dim3(256), 0, st, p.list, p.s + R_RN, p.dirty,
-                               (uint8_t)0);
-            st_local.h_recomputes += rn;
+            const uint32_t *rlist = p.list, *rcount = p.s + R_RN;
+            uint32_t rcnt = rn;
+            if (gated) {
+                // the network defers the recomputes it expects to find far above the level
+                if ((rc = gate_pass(ctx, g, gate->mlp, gate->margin, p.alive, p.dm, p.list, rn, p.lb, p.d, p.dirty,
+                                    p.part, p.s, gate_x, gate_y, gate_list)))
+                    return rc;
+                e = hipMemcpyAsync(hs + R_GKEEP, p.s + R_GKEEP, 4, hipMemcpyDeviceToHost, st);
+                if (e == hipSuccess) e = hipStreamSynchronize(st);
+                if (e != hipSuccess) return check_hip(ctx, e, "gate readback");
+                rcnt = hs[R_GKEEP];
+                st_local.gate_deferrals += rn - rcnt;
+                if (rcnt == 0) continue;
+                rlist = gate_list;
+                rcount = p.s + R_GKEEP;
+            }
+            if ((rc = msbfs_degrees(ctx, g, p.alive, h, rlist, rcnt, nullptr, 1, p.d))) return rc;
+            hipLaunchKernelGGL(set_flag_kernel, dim3(grid_n), dim3(256), 0, st, rlist, rcount, p.dirty, (uint8_t)0);
+            st_local.h_recomputes += rcnt;
         }
         if ((rc = peel_round_common(ctx, g, h, p, bounded, r, core, peel_round, grid_n))) return rc;
         const uint32_t np = hs[R_CNT];

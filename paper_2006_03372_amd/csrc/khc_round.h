@@ -7,7 +7,9 @@
 // the removed set), then removal of P.
 //
 // Round scalars (u32 array s): s[R_K] level, s[R_KNEW] level of this round,
-// s[R_RN] recompute count, s[R_LIVE] live vertices, s[R_CNT + j] vertices put
+// s[R_RN] recompute count, s[R_LIVE] live vertices, s[R_SMIN] (sampling
+// mode) nearest queue level holding a sampled vertex, s[R_GKEEP] (learned
+// gate) recomputes kept by the gate, s[R_CNT + j] vertices put
 // on the queue at BFS level j (level 0 = P), s[R_CNT + h + 1 + j] push items
 // of level j; u64 array s64[j]: total degree of the level-j vertices.
 // queue = [P | level 1 | ... | level h]; a queued row with more than
@@ -25,7 +27,7 @@ namespace rnd {
 namespace {  // each including source gets its own copy of the kernels
 
 constexpr int kMinBlocks = 1024;
-enum : int { R_K = 0, R_KNEW = 1, R_RN = 2, R_LIVE = 3, R_CNT = 8 };
+enum : int { R_K = 0, R_KNEW = 1, R_RN = 2, R_LIVE = 3, R_SMIN = 4, R_GKEEP = 5, R_CNT = 8 };
 constexpr uint32_t kPushArcs = 256;  // arcs per push item
 
 inline int round_nscal(uint32_t h) { return R_CNT + 2 * (int)h + 3; }
@@ -57,7 +59,7 @@ inline RoundGraph round_graph(const khc_graph *g) {
 // Per-block minimum of key(v) = (dirty && dirty[v]) ? lb[v] : d[v] over
 // live v into part[blockIdx.x] (grid must be kMinBlocks).  Block 0 also
 // clears the counters of the coming select / collect.
-__global__ void keymin_kernel(uint32_t n, const uint8_t *alive, const uint8_t *dirty, const uint32_t *d,
+[[maybe_unused]] __global__ void keymin_kernel(uint32_t n, const uint8_t *alive, const uint8_t *dirty, const uint32_t *d,
                               const uint32_t *lb, uint32_t *part, uint32_t *s, unsigned long long *s64,
                               int h) {
     __shared__ uint32_t red[4];
@@ -82,7 +84,10 @@ __global__ void keymin_kernel(uint32_t n, const uint8_t *alive, const uint8_t *d
             s[R_CNT + j] = 0;
             s[R_CNT + h + 1 + j] = 0;
             s64[j] = 0;
-            if (j == 0) s[R_RN] = 0;
+            if (j == 0) {
+                s[R_RN] = 0;
+                s[R_GKEEP] = 0;
+            }
         }
 }
 
@@ -141,7 +146,7 @@ __device__ __forceinline__ void add_items(uint32_t x, uint64_t deg, int L, int h
 // ones, so a dirty vertex with d <= k leaves at this level without a
 // recompute; the dirty vertices left open were resolved by the cleaning
 // loop (their lower bound exceeds k).
-__global__ void select_kernel(uint32_t n, const uint64_t *row_ptr, const uint8_t *alive, const uint8_t *dirty,
+[[maybe_unused]] __global__ void select_kernel(uint32_t n, const uint64_t *row_ptr, const uint8_t *alive, const uint8_t *dirty,
                               const uint32_t *d, const uint32_t *part, uint32_t *mark, uint32_t *core,
                               uint32_t *round, uint32_t r, uint32_t *queue, uint32_t *s,
                               unsigned long long *s64, uint2 *items, int h) {
@@ -182,7 +187,7 @@ __device__ __forceinline__ void queue_take(bool take, uint32_t y, const RoundGra
 // every unqueued live row looks for a neighbour of level L-1, heavy rows by
 // chunks (one wavefront each), rows above kMidDeg arcs by groups of 8
 // lanes, the rest one lane each, all stopping at the first hit.
-__global__ void affected_kernel(RoundGraph g, const uint8_t *alive, uint32_t *mark, uint32_t *queue, uint32_t *s,
+[[maybe_unused]] __global__ void affected_kernel(RoundGraph g, const uint8_t *alive, uint32_t *mark, uint32_t *queue, uint32_t *s,
                                 unsigned long long *s64, uint2 *items, int L, int h) {
     uint32_t begin = 0, ibegin = 0;
     for (int j = 0; j + 1 < L; ++j) {
@@ -307,7 +312,7 @@ __global__ void affected_kernel(RoundGraph g, const uint8_t *alive, uint32_t *ma
 // bounds on the (h-1)-degrees), the vertices at distance h-1 from P lower
 // their bound by |P|: their (h-1)-ball reaches P only at its rim, so they
 // can lose the vertices of P and nothing else.
-__global__ void kill_kernel(const uint32_t *queue, uint32_t *s, uint8_t *alive, uint32_t *dm, int h) {
+[[maybe_unused]] __global__ void kill_kernel(const uint32_t *queue, uint32_t *s, uint8_t *alive, uint32_t *dm, int h) {
     const uint32_t np = s[R_CNT];
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < np; i += gridDim.x * blockDim.x)
         alive[queue[i]] = 0;
@@ -328,7 +333,7 @@ __global__ void kill_kernel(const uint32_t *queue, uint32_t *s, uint8_t *alive, 
 
 // Clear the marks of every queued vertex; optionally set flag[] on the
 // affected part (queue entries after P).
-__global__ void finish_kernel(const uint32_t *queue, const uint32_t *s, int h, uint32_t *mark, uint8_t *flag,
+[[maybe_unused]] __global__ void finish_kernel(const uint32_t *queue, const uint32_t *s, int h, uint32_t *mark, uint8_t *flag,
                               uint8_t value) {
     uint32_t np = s[R_CNT], tot = 0;
     for (int j = 0; j <= h; ++j) tot += s[R_CNT + j];

@@ -11,10 +11,18 @@
 // sel0 / d0, in integer arithmetic.  Peeling runs on est as the exact
 // driver runs on the h-degree (level k = max(k, min est), remove every
 // est <= k), and after each round the live vertices within h hops of the
-// removed set recount their sampled vertices with the masked multi-source
+// removed set P recount their sampled vertices with the masked multi-source
 // BFS (a reached row counts only if it is sampled).  sel never grows under
 // removal, so est does not either and the result does not depend on the
 // removal order; the CPU oracle computes the same numbers one by one.
+//
+// Only part of that set can lose a sampled vertex.  A vertex x leaves the
+// h-ball of u, at distance j from P, only if every path of at most h hops
+// from u to x runs through P, so x lies within h - j hops of P.  If no
+// sampled vertex lies within h - j hops of P, sel(u) is unchanged.  With r0
+// the smallest distance from P of a sampled vertex (r0 < h), the vertices
+// at distance 1 .. h - r0 are recounted and the rest keep their counts; no
+// vertex is recounted when no sampled vertex lies within h - 1 hops.
 #include <chrono>
 #include <cstring>
 
@@ -41,6 +49,19 @@ __global__ void sample_estimate_kernel(const uint32_t *list, uint32_t count, con
     for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < count; i += gridDim.x * blockDim.x) {
         const uint32_t v = list ? list[i] : i;
         est[v] = sel0[v] ? (uint32_t)(((uint64_t)sel[v] * d0[v]) / sel0[v]) : d0[v];
+    }
+}
+
+// s[R_SMIN] = min(s[R_SMIN], level) over the sampled vertices of queue levels
+// 0 .. h-1 (level boundaries from the round counters).
+__global__ void sample_ring_kernel(const uint32_t *queue, uint32_t *s, int h, const uint8_t *sampled) {
+    uint32_t end = 0;
+    for (int j = 0; j < h; ++j) end += s[R_CNT + j];
+    for (uint32_t i = blockIdx.x * blockDim.x + threadIdx.x; i < end; i += gridDim.x * blockDim.x) {
+        if (!sampled[queue[i]]) continue;
+        uint32_t j = 0, at = s[R_CNT];
+        while (i >= at) at += s[R_CNT + ++j];
+        atomicMin(&s[R_SMIN], j);
     }
 }
 
@@ -133,6 +154,9 @@ extern "C" int khcore_decompose_sampled(khc_ctx *ctx, const khc_graph *g, uint32
         for (uint32_t lev = 1; lev <= h; ++lev)
             hipLaunchKernelGGL(affected_kernel, dim3(wgrid), dim3(256), 0, st, rg, alive, mark, queue, scal, s64,
                                items, (int)lev, (int)h);
+        fill_u32(ctx, scal + R_SMIN, h, 1);
+        hipLaunchKernelGGL(sample_ring_kernel, dim3(gn), dim3(256), 0, st, (const uint32_t *)queue, scal, (int)h,
+                           sampled);
         hipLaunchKernelGGL(kill_kernel, dim3(gn), dim3(256), 0, st, queue, scal, alive, (uint32_t *)nullptr, 0);
         hipError_t e = hipMemcpyAsync(hs, scal, (size_t)nscal * 4, hipMemcpyDeviceToHost, st);
         if (e == hipSuccess) e = hipStreamSynchronize(st);
@@ -142,13 +166,17 @@ extern "C" int khcore_decompose_sampled(khc_ctx *ctx, const khc_graph *g, uint32
         uint32_t tot = 0;
         for (uint32_t j = 0; j <= h; ++j) tot += hs[R_CNT + j];
         const uint32_t na = tot - np;
-        if (na) {
-            // recount the sampled vertices of every affected ball, then rescale
-            if ((rc = msbfs_masked_counts(ctx, g, alive, h, queue + np, na, sampled, sel))) return rc;
-            hipLaunchKernelGGL(sample_estimate_kernel, dim3(sgrid(ctx, na)), dim3(256), 0, st,
-                               (const uint32_t *)(queue + np), na, (const uint32_t *)sel, (const uint32_t *)sel0,
+        // levels 1 .. h - r0 can lose a sampled vertex (r0 = hs[R_SMIN])
+        const uint32_t r0 = hs[R_SMIN];
+        uint32_t nr = 0;
+        for (uint32_t j = 1; r0 < h && j <= h - r0; ++j) nr += hs[R_CNT + j];
+        if (nr) {
+            // recount the sampled vertices of those balls, then rescale
+            if ((rc = msbfs_masked_counts(ctx, g, alive, h, queue + np, nr, sampled, sel))) return rc;
+            hipLaunchKernelGGL(sample_estimate_kernel, dim3(sgrid(ctx, nr)), dim3(256), 0, st,
+                               (const uint32_t *)(queue + np), nr, (const uint32_t *)sel, (const uint32_t *)sel0,
                                (const uint32_t *)d0, est);
-            sl.h_recomputes += na;
+            sl.h_recomputes += nr;
         }
         hipLaunchKernelGGL(finish_kernel, dim3(gn), dim3(256), 0, st, queue, scal, (int)h, mark, (uint8_t *)nullptr,
                            (uint8_t)0);

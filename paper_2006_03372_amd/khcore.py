@@ -42,7 +42,8 @@ EXPORTED = [
     "khc_mlp_create", "khc_mlp_destroy", "khc_mlp_set_params", "khc_mlp_get_params",
     "khc_mlp_forward", "khc_mlp_gradient", "khc_mlp_train", "khc_features", "khcore_decompose_approx",
     "khc_persist_profile_read", "khc_set_progress", "khc_autotune", "khc_mlp_save", "khc_mlp_load",
-    "khc_mlp_get_moments", "khdeg_compute_noalloc", "khcore_decompose_sampled",
+    "khc_mlp_get_moments", "khdeg_compute_noalloc", "khcore_decompose_sampled", "khc_gate_features",
+    "khcore_decompose_gated",
 ]
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32)
@@ -96,7 +97,8 @@ class Stats(ctypes.Structure):
                 ("hm1_recomputes", ctypes.c_uint64), ("bfs_batches", ctypes.c_uint64),
                 ("affected_total", ctypes.c_uint64), ("max_level", ctypes.c_uint32),
                 ("width_words", ctypes.c_uint32), ("wall_ms", ctypes.c_double),
-                ("local_rounds", ctypes.c_uint64), ("local_sources", ctypes.c_uint64)]
+                ("local_rounds", ctypes.c_uint64), ("local_sources", ctypes.c_uint64),
+                ("gate_deferrals", ctypes.c_uint64)]
 
     def as_dict(self):
         return {name: getattr(self, name) for name, _ in self._fields_}
@@ -142,6 +144,8 @@ def load_library(path: str = LIB_PATH):
         "khc_features": ([P, P, P, u32, P, P, P], i32),
         "khcore_decompose_approx": ([P, P, u32, P, P, P, ctypes.POINTER(Stats)], i32),
         "khcore_decompose_sampled": ([P, P, u32, P, P, P, ctypes.POINTER(Stats)], i32),
+        "khc_gate_features": ([P, P, P, u32, P, P], i32),
+        "khcore_decompose_gated": ([P, P, u32, P, ctypes.c_float, P, P, ctypes.POINTER(Stats)], i32),
         "khc_persist_profile_read": ([P, P, P, i32], i32),
         "khc_set_progress": ([P, PROGRESS_FN, P, u32], i32),
         "khc_autotune": ([P, P, u32, u32, ctypes.POINTER(Tune)], i32),
@@ -285,6 +289,26 @@ class Context:
         self._check(self.lib.khcore_decompose_sampled(self.handle, graph.handle, h, _dptr(sampled), _dptr(core),
                                                       _dptr(est), ctypes.byref(st)))
         return core, est, st.as_dict()
+
+    def gate_features(self, graph: "Graph", h: int, dm, alive=None):
+        """Gate features X float32 [n, 8] of G(alive) from dm, the
+        (h-1)-degrees or lower bounds on them (device tensor)."""
+        torch = _torch()
+        X = torch.empty((graph.n, 8), dtype=torch.float32, device=graph.device)
+        self._check(self.lib.khc_gate_features(self.handle, graph.handle, _dptr(alive), h, _dptr(dm), _dptr(X)))
+        return X
+
+    def core_gated(self, graph: "Graph", h: int, mlp=None, margin: float = 0.0, with_round: bool = False):
+        """Bounded-schedule decomposition with the learned recompute gate:
+        (core, round or None, stats); mlp None gives the exact result."""
+        torch = _torch()
+        core = torch.empty(graph.n, dtype=torch.int32, device=graph.device)
+        rnd = torch.empty(graph.n, dtype=torch.int32, device=graph.device) if with_round else None
+        st = Stats()
+        self._check(self.lib.khcore_decompose_gated(self.handle, graph.handle, h,
+                                                    None if mlp is None else mlp.handle, float(margin),
+                                                    _dptr(core), _dptr(rnd), ctypes.byref(st)))
+        return core, rnd, st.as_dict()
 
     def validate(self, row_ptr, col, n: int) -> int:
         """Validate a device CSR; returns the status code (0 = ok)."""

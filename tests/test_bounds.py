@@ -8,7 +8,10 @@ removed sets P:
   from P loses at most |{v : dist(P, v) <= h - j}| vertices of its h-ball
   (P counted); vertices farther than h keep their h-degree;
 * the same at radius h - 1: a vertex at distance h - 1 from P loses at most
-  |P| from its (h-1)-ball.
+  |P| from its (h-1)-ball;
+* the sampling mode's recount rule: a vertex at distance j from P loses
+  only sampled vertices within h - j hops of P, so its sampled count is
+  unchanged when there are none.
 """
 import numpy as np
 import pytest
@@ -74,6 +77,47 @@ def test_decrement_bound(kind, n, h, seed, frac):
                 assert before[u] - now[u] <= ring[r - j], (u, r, j)
                 if j == r:  # the outermost ring loses P at most
                     assert before[u] - now[u] <= P.size, (u, r)
+
+
+def _ball(g, alive, u, h):
+    """Vertices other than u within h hops of u over live vertices."""
+    seen = {int(u)}
+    frontier = [int(u)]
+    for _ in range(h):
+        nxt = []
+        for x in frontier:
+            for y in g.col[g.row_ptr[x]:g.row_ptr[x + 1]]:
+                y = int(y)
+                if alive[y] and y not in seen:
+                    seen.add(y)
+                    nxt.append(y)
+        frontier = nxt
+    seen.discard(int(u))
+    return seen
+
+
+@settings(max_examples=40, deadline=None)
+@given(kind=st.sampled_from(["er", "cl"]), n=st.integers(8, 50), h=st.integers(1, 4),
+       seed=st.integers(0, 10_000), frac=st.floats(0.02, 0.3), rate=st.floats(0.05, 0.5))
+def test_sampled_recount_rule(kind, n, h, seed, frac, rate):
+    g = _graph(kind, n, seed)
+    rng = np.random.default_rng(seed + 2)
+    alive = (rng.random(g.n) < 0.9).astype(np.uint8)
+    sampled = rng.random(g.n) < rate
+    live = np.flatnonzero(alive)
+    if live.size == 0:
+        return
+    P = rng.choice(live, size=max(1, int(frac * live.size)), replace=False)
+    after = alive.copy()
+    after[P] = 0
+    dist = _dist_from_set(g, alive.astype(bool), P)
+    for u in np.flatnonzero(after):
+        j = int(min(dist[u], h + 1))
+        lost = {x for x in _ball(g, alive, u, h) - _ball(g, after, u, h) if sampled[x]}
+        # every lost sampled vertex lies within h - j hops of P
+        assert all(dist[x] <= h - j for x in lost), (u, j, lost)
+        if not np.any(sampled & (dist <= h - j) & alive.astype(bool)):
+            assert not lost
 
 
 @pytest.mark.parametrize("h", [2, 3, 4])

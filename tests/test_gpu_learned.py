@@ -215,6 +215,37 @@ def test_learned_mode_beats_bounds_only(ctx, h):
     net.close()
 
 
+def test_network_on_rmat_h4(ctx):
+    """On the R-MAT family at h = 4 the exact lower bound is nearly tight, so
+    the approximate mode's clamped estimate mostly equals it and the network
+    cannot gain there.  The network itself is still not degenerate: trained
+    on small R-MAT graphs, its raw estimates on an unseen one differ from the
+    lower bound on most vertices and track the exact 4-hop degree."""
+    import torch
+    from paper_2006_03372_amd import learned
+    train = [synth.rmat(11, 8, seed=400 + i) for i in range(6)]
+    X, t = learned.training_set(ctx, train, 4)
+    net = ctx.mlp(seed=7)
+    net.train(X, t, epochs=25, batch=2048, lr=2e-3, seed=1)
+    g = synth.rmat(11, 8, seed=1)
+    gr = ctx.graph(g)
+    Xt, lb, ub = ctx.features(gr, 4)
+    d = ctx.hdeg(gr, 4)
+    y = net.forward(Xt)
+    gr.close()
+    net.close()
+    est = np.expm1(8.0 * y.cpu().numpy().astype(np.float64))
+    lb, ub, d = (a.cpu().numpy().view(np.uint32).astype(np.float64) for a in (lb, ub, d))
+    live = d > 0
+    rel_net = np.abs(est[live] - d[live]) / d[live]
+    rel_lb = (d[live] - lb[live]) / d[live]
+    clamped_at_lb = np.mean(np.clip(np.rint(est[live]), lb[live], ub[live]) == lb[live])
+    print(f"median relative error: network {np.median(rel_net):.4f}, lower bound {np.median(rel_lb):.4f}; "
+          f"clamped estimate at the lower bound on {clamped_at_lb:.3f} of vertices", flush=True)
+    assert np.mean(np.rint(est[live]) != lb[live]) > 0.5
+    assert np.median(rel_net) < 0.1
+
+
 def test_training_is_reproducible(ctx):
     """Gradients are summed in a fixed order, so two runs from the same seeds
     end with the same parameters bit for bit."""

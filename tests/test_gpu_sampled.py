@@ -35,6 +35,9 @@ CASES = [
     ("r-mat 12", lambda: synth.rmat(12, 8, seed=2), 2, 0.2),
     ("r-mat 12", lambda: synth.rmat(12, 8, seed=2), 3, 0.05),
     ("star 700", lambda: synth.star(700), 2, 0.1),
+    ("r-mat 12", lambda: synth.rmat(12, 8, seed=2), 1, 0.1),
+    ("chung-lu 3000 mean 4", lambda: synth.chung_lu(3000, 4.0, 2.5, seed=8), 2, 0.02),
+    ("chung-lu 3000 mean 4", lambda: synth.chung_lu(3000, 4.0, 2.5, seed=8), 4, 0.02),
 ]
 
 
@@ -65,3 +68,22 @@ def test_everything_sampled_is_exact(ctx):
     gr.close()
     assert (_u32(c) == _u32(exact)).all()
     assert (_u32(c) == oracle.peel(g, 2)[0]).all()
+
+
+def test_sparse_sample_skips_recounts(ctx):
+    """A vertex at distance j from the removed set can only lose sampled
+    vertices within h - j hops of it: with a sparse sample most affected
+    vertices keep their counts, and the result still equals the oracle's
+    (which recounts every affected vertex)."""
+    import torch
+    g = synth.chung_lu(5000, 6.0, 2.5, seed=3)
+    s = _sample(g.n, 0.03, 5)
+    gr = ctx.graph(g)
+    c, est, st = ctx.core_sampled(gr, 2, torch.from_numpy(s).cuda(), with_estimate=True)
+    gr.close()
+    c_ref, est_ref = oracle.peel_sampled(g, 2, s)
+    assert (_u32(c) == c_ref).all() and (_u32(est) == est_ref).all()
+    print(st, flush=True)
+    # h_recomputes also counts the two initial passes over every vertex with a neighbour
+    recounts = st["h_recomputes"] - 2 * int(np.count_nonzero(g.degrees()))
+    assert 0 <= recounts < st["affected_total"] // 2, st
