@@ -103,6 +103,10 @@ const char *khc_last_error(const khc_ctx *ctx);
                                      degree times a width-dependent factor is below the arc count;
                                      c in 1..4096 = push while (frontier arcs x non-zero source words)
                                      times c is below (arcs x width + 4 x rows), the pull's gathers */
+#define KHC_OPT_TUNE_REPEATS 12  /* autotuner trials per candidate, the median kept (1..15; default 3)    */
+#define KHC_OPT_TUNE_CACHE 13    /* 1 = khc_autotune reuses the choice made on this context for a graph of
+                                     the same size class (default); 0 = always time, and forget the
+                                     cached choices                                                   */
 int khc_set_option(khc_ctx *ctx, int option, int64_t value);
 
 /* Kernel timing collected while KHC_OPT_PROFILE is 1, per kernel class:
@@ -281,13 +285,17 @@ int khcore_decompose_sampled(khc_ctx *ctx, const khc_graph *g, uint32_t h, const
 /* ---- autotuner --------------------------------------------------------- */
 
 /* Picks the BFS source-block width (uint64 words per vertex, 64 sources
- * each) and the wavefronts per CU for decompositions of g at h by timing a
- * trial of each candidate: the decomposition cut after `rounds` peeling
+ * each) and the wavefronts per CU for decompositions of g at h by timing
+ * trials of each candidate: the decomposition cut after `rounds` peeling
  * rounds (KHC_OPT_ROUND_LIMIT), run on the driver khcore_decompose would use
- * for g.  Candidates: widths 8, 16, 32 and 4, 8, 16 wavefronts per CU.  The
- * fastest candidate is set on ctx (KHC_OPT_MAX_WIDTH or
- * KHC_OPT_PERSIST_WIDTH, and KHC_OPT_WAVES_PER_CU); every trial is reported
- * in *out (host, or NULL).  Synchronous; allocates a trial output buffer. */
+ * for g, KHC_OPT_TUNE_REPEATS times, the median kept.  Candidates: widths 8,
+ * 16, 32 and 4, 8, 16 wavefronts per CU.  The fastest candidate is set on
+ * ctx (KHC_OPT_MAX_WIDTH or KHC_OPT_PERSIST_WIDTH, and
+ * KHC_OPT_WAVES_PER_CU) and remembered for the graph's size class (driver,
+ * h, rounds, and the powers of two at or above the vertex and arc counts);
+ * a later call for the same class applies it without trials
+ * (KHC_OPT_TUNE_CACHE).  Every median is reported in *out (host, or NULL).
+ * Synchronous; allocates a trial output buffer when it times. */
 #define KHC_TUNE_MAX 16
 typedef struct {
     uint32_t width_words;              /* chosen width                              */
@@ -296,7 +304,9 @@ typedef struct {
     uint32_t candidates;               /* trials run                                */
     uint32_t cand_width[KHC_TUNE_MAX];
     uint32_t cand_waves[KHC_TUNE_MAX];
-    double trial_ms[KHC_TUNE_MAX];     /* wall time of each trial                   */
+    double trial_ms[KHC_TUNE_MAX];     /* median wall time of each candidate's trials */
+    uint32_t repeats;                  /* trials per candidate                      */
+    uint32_t cached;                   /* 1: applied from the cache, no trials      */
 } khc_tune;
 int khc_autotune(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t rounds, khc_tune *out);
 

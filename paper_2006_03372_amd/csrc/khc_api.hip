@@ -394,6 +394,14 @@ int khc_set_option(khc_ctx *ctx, int option, int64_t value) {
             if (value < 0 || value > 4096) return set_error(ctx, KHC_EINVAL, "push cost must be in [0, 4096]");
             ctx->push_cost = (int)value;
             return KHC_OK;
+        case KHC_OPT_TUNE_REPEATS:
+            if (value < 1 || value > 15) return set_error(ctx, KHC_EINVAL, "tune repeats must be in [1, 15]");
+            ctx->tune_repeats = (int)value;
+            return KHC_OK;
+        case KHC_OPT_TUNE_CACHE:
+            ctx->tune_cache_on = value ? 1 : 0;
+            if (!value) ctx->tune_cache.clear();
+            return KHC_OK;
         case KHC_OPT_ROUND_LIMIT:
             if (value < 0 || value > 0xFFFFFFFFll) return set_error(ctx, KHC_EINVAL, "round limit must be >= 0");
             ctx->round_limit = (uint32_t)value;

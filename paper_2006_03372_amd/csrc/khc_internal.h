@@ -5,6 +5,7 @@
 #include <stdint.h>
 
 #include <chrono>
+#include <map>
 #include <string>
 #include <vector>
 
@@ -63,6 +64,9 @@ struct khc_ctx {
     int waves_per_cu = 16;
     uint32_t round_limit = 0;  // 0: peel to the end
     int push_cost = 0;         // BFS push/pull rule (KHC_OPT_PUSH_COST)
+    int tune_repeats = 3;      // autotuner trials per candidate
+    int tune_cache_on = 1;     // autotuner reuses choices per size class
+    std::map<uint64_t, std::pair<int, int>> tune_cache;  // size class -> (width, waves per CU)
     // workspace
     std::vector<khc::DevBuf> bufs;
     uint64_t ws_bytes = 0;

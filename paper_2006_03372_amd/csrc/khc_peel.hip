@@ -102,9 +102,22 @@ __global__ void lower_bound_kernel(const uint32_t *list, const uint32_t *s, int 
         if (live) {
             const uint64_t rb = row_ptr[u], re0 = row_ptr[u + 1];
             const uint64_t re = re0 - rb > kLbArcs ? rb + kLbArcs : re0;
-            for (uint64_t a = rb + sub; a < re; a += 16) {
-                const uint32_t w = col[a];
-                if (alive[w] && dm[w] > m) m = dm[w];
+            // four arcs per lane and step, their loads independent; slots
+            // past the end repeat the step's first arc (max is idempotent).
+            // Measured 2-3% off the R-MAT-18 and Chung-Lu 200K h = 3
+            // decompositions against one arc per step.
+            for (uint64_t a = rb + sub; a < re; a += 64) {
+                uint32_t w[4];
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint64_t ak = a + 16u * k;
+                    w[k] = col[ak < re ? ak : a];
+                }
+#pragma unroll
+                for (int k = 0; k < 4; ++k) {
+                    const uint32_t x = dm[w[k]];
+                    if (alive[w[k]] && x > m) m = x;
+                }
             }
         }
         for (int off = 8; off > 0; off >>= 1) {

@@ -33,6 +33,8 @@ OPT_PERSIST_WIDTH = 8
 OPT_BARRIER_TIMEOUT = 9
 OPT_ROUND_LIMIT = 10
 OPT_PUSH_COST = 11
+OPT_TUNE_REPEATS = 12
+OPT_TUNE_CACHE = 13
 
 EXPORTED = [
     "khc_create", "khc_destroy", "khc_last_error", "khc_set_option", "khc_profile_read",
@@ -61,12 +63,13 @@ class Tune(ctypes.Structure):
     _fields_ = [("width_words", ctypes.c_uint32), ("waves_per_cu", ctypes.c_uint32),
                 ("persistent", ctypes.c_uint32), ("candidates", ctypes.c_uint32),
                 ("cand_width", ctypes.c_uint32 * TUNE_MAX), ("cand_waves", ctypes.c_uint32 * TUNE_MAX),
-                ("trial_ms", ctypes.c_double * TUNE_MAX)]
+                ("trial_ms", ctypes.c_double * TUNE_MAX), ("repeats", ctypes.c_uint32),
+                ("cached", ctypes.c_uint32)]
 
     def as_dict(self):
         k = self.candidates
         return {"width_words": self.width_words, "waves_per_cu": self.waves_per_cu,
-                "persistent": bool(self.persistent),
+                "persistent": bool(self.persistent), "repeats": self.repeats, "cached": bool(self.cached),
                 "trials": [(self.cand_width[i], self.cand_waves[i], self.trial_ms[i]) for i in range(k)]}
 
 
@@ -214,7 +217,9 @@ class Context:
 
     def autotune(self, graph: "Graph", h: int, rounds: int = 64) -> dict:
         """Time trial decompositions (cut after `rounds` rounds) over the
-        width x waves-per-CU candidates and keep the fastest on this context."""
+        width x waves-per-CU candidates, OPT_TUNE_REPEATS times each, and keep
+        the smallest median on this context (or apply the choice cached for
+        the graph's size class)."""
         t = Tune()
         self._check(self.lib.khc_autotune(self.handle, graph.handle, h, rounds, ctypes.byref(t)))
         return t.as_dict()

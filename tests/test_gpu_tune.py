@@ -85,3 +85,37 @@ def test_autotune_batched(ctx):
         off += g.n
     ctx.set_option(khcore.OPT_PERSIST_WIDTH, 32)
     ctx.set_option(khcore.OPT_WAVES_PER_CU, 16)
+
+
+def test_autotune_median_and_cache(ctx):
+    """Each candidate is timed OPT_TUNE_REPEATS times (the median kept); a
+    second graph of the same size class gets the cached choice without
+    trials, and turning the cache off times again."""
+    from paper_2006_03372_amd import khcore
+    a = ctx.graph(synth.chung_lu(3000, 8.0, 2.5, seed=31))
+    b = ctx.graph(synth.chung_lu(3000, 8.0, 2.5, seed=32))
+    try:
+        ctx.set_option(khcore.OPT_TUNE_REPEATS, 5)
+        ta = ctx.autotune(a, 2, rounds=12)
+        assert not ta["cached"] and ta["repeats"] == 5 and len(ta["trials"]) == 9
+        best = min(ta["trials"], key=lambda x: x[2])
+        assert (ta["width_words"], ta["waves_per_cu"]) == best[:2]
+        # same vertex count, arc counts below the same power of two: cached
+        assert a.n == b.n
+        ctx.set_option(khcore.OPT_MAX_WIDTH, 1)
+        tb = ctx.autotune(b, 2, rounds=12)
+        assert tb["cached"] and tb["trials"] == []
+        assert (tb["width_words"], tb["waves_per_cu"]) == (ta["width_words"], ta["waves_per_cu"])
+        c, _, st = ctx.core(b, 2)
+        assert st["width_words"] == ta["width_words"]
+        # another h is another class
+        assert not ctx.autotune(b, 3, rounds=12)["cached"]
+        ctx.set_option(khcore.OPT_TUNE_CACHE, 0)
+        assert not ctx.autotune(b, 2, rounds=12)["cached"]
+    finally:
+        ctx.set_option(khcore.OPT_TUNE_CACHE, 1)
+        ctx.set_option(khcore.OPT_TUNE_REPEATS, 3)
+        ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
+        ctx.set_option(khcore.OPT_WAVES_PER_CU, 16)
+        a.close()
+        b.close()
