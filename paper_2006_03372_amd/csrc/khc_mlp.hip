@@ -1,5 +1,6 @@
 // Small MLP for the learned approximate mode: 8 -> 64 -> 64 -> 1 with ReLU,
-// BF16 weights and activations into MFMA (V_MFMA_F32_16X16X16_BF16),
+// BF16 weights and activations into MFMA (V_MFMA_F32_16X16X32_BF16 for the
+// 64-long contractions, V_MFMA_F32_16X16X16_BF16 for the 16-long ones),
 // FP32 accumulation, FP32 biases, FP32 master weights and Adam (gfx950).
 //
 // It maps the 8 log-scaled cheap features of a vertex to its log-scaled
@@ -7,11 +8,15 @@
 // IV-C); this estimator is trained on exact h-degrees the library itself
 // computes, and the exact peeling stays the reference for its error.
 //
-// MFMA 16x16x16 (bf16 inputs) operand layout, lane l of a wavefront,
-// r = l % 16, q = l / 16:
-//   A (16 x 16, M x K): a[i] = A[r][4q + i]
-//   B (16 x 16, K x N): b[i] = B[4q + i][r]
-//   D (16 x 16, M x N): d[i] = D[4q + i][r]
+// MFMA operand layouts (bf16 inputs), lane l of a wavefront, r = l % 16,
+// q = l / 16, measured on the device:
+//   16x16x16: A (16 x 16, M x K): a[i] = A[r][4q + i], i < 4
+//             B (16 x 16, K x N): b[i] = B[4q + i][r]
+//   16x16x32: A (16 x 32): a[i] = A[r][8q + i], i < 8; B (32 x 16): b[i] = B[8q + i][r]
+//   both:     D (16 x 16, M x N): d[i] = D[4q + i][r]
+// The contractions over the 64 hidden units (layers 2 and 3 forward, dH1
+// backward) take two K = 32 steps; those over the 16 rows of a tile (dW1,
+// dW2) and over the 8 features padded to 16 (layer 1) take one K = 16 step.
 // A wavefront processes 16 rows (vertices) per tile.  Activations move
 // between layers through LDS, where the D layout of one layer is re-read
 // in the A layout of the next.
@@ -31,6 +36,8 @@ namespace khc {
 namespace {
 
 typedef short bf16x4 __attribute__((ext_vector_type(4)));
+typedef short bf16x8 __attribute__((ext_vector_type(8)));
+typedef __bf16 bf16v8 __attribute__((ext_vector_type(8)));
 typedef float f32x4 __attribute__((ext_vector_type(4)));
 
 constexpr int kIn = 8, kHid = 64;
@@ -52,6 +59,10 @@ __device__ __forceinline__ float bf2f(short b) { return __uint_as_float(((uint32
 
 __device__ __forceinline__ f32x4 mfma(bf16x4 a, bf16x4 b, f32x4 c) {
     return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f32x4 mfma32(bf16x8 a, bf16x8 b, f32x4 c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(__builtin_bit_cast(bf16v8, a), __builtin_bit_cast(bf16v8, b), c, 0,
+                                                   0, 0);
 }
 
 // Forward pass of one 16-row tile (one wavefront).  X rows are given by
@@ -96,13 +107,13 @@ __device__ void tile_forward(const float *X, const uint32_t *ridx, uint32_t row0
     __builtin_amdgcn_wave_barrier();
     for (int tn = 0; tn < 4; ++tn) {
         f32x4 acc{0.f, 0.f, 0.f, 0.f};
-        for (int s = 0; s < 4; ++s) {
-            bf16x4 aa, b;
-            for (int i = 0; i < 4; ++i) {
-                aa[i] = t.h1[r][16 * s + 4 * q + i];
-                b[i] = W2[(16 * tn + r) * kHid + 16 * s + 4 * q + i];
+        for (int s = 0; s < 2; ++s) {
+            bf16x8 aa, b;
+            for (int i = 0; i < 8; ++i) {
+                aa[i] = t.h1[r][32 * s + 8 * q + i];
+                b[i] = W2[(16 * tn + r) * kHid + 32 * s + 8 * q + i];
             }
-            acc = mfma(aa, b, acc);
+            acc = mfma32(aa, b, acc);
         }
         const float bias = params[ob2 + 16 * tn + r];
         for (int i = 0; i < 4; ++i) {
@@ -113,13 +124,13 @@ __device__ void tile_forward(const float *X, const uint32_t *ridx, uint32_t row0
     __builtin_amdgcn_s_waitcnt(0);
     __builtin_amdgcn_wave_barrier();
     f32x4 acc{0.f, 0.f, 0.f, 0.f};
-    for (int s = 0; s < 4; ++s) {
-        bf16x4 aa, b;
-        for (int i = 0; i < 4; ++i) {
-            aa[i] = t.h2[r][16 * s + 4 * q + i];
-            b[i] = W3p[r * kHid + 16 * s + 4 * q + i];
+    for (int s = 0; s < 2; ++s) {
+        bf16x8 aa, b;
+        for (int i = 0; i < 8; ++i) {
+            aa[i] = t.h2[r][32 * s + 8 * q + i];
+            b[i] = W3p[r * kHid + 32 * s + 8 * q + i];
         }
-        acc = mfma(aa, b, acc);
+        acc = mfma32(aa, b, acc);
     }
     if (r == 0)
         for (int i = 0; i < 4; ++i) t.y[4 * q + i] = acc[i] + params[ob3];
@@ -219,13 +230,13 @@ __global__ __launch_bounds__(256) void mlp_backward_kernel(const float *X, const
         short dh1v[4][4];
         for (int tn = 0; tn < 4; ++tn) {
             f32x4 acc{0.f, 0.f, 0.f, 0.f};
-            for (int s = 0; s < 4; ++s) {
-                bf16x4 a, b;
-                for (int i = 0; i < 4; ++i) {
-                    a[i] = t.h2[r][16 * s + 4 * q + i];        // A[row][o] = dH2
-                    b[i] = w2t[16 * s + 4 * q + i][16 * tn + r];  // B[o][i] = W2[o][i]
+            for (int s = 0; s < 2; ++s) {
+                bf16x8 a, b;
+                for (int i = 0; i < 8; ++i) {
+                    a[i] = t.h2[r][32 * s + 8 * q + i];        // A[row][o] = dH2
+                    b[i] = w2t[32 * s + 8 * q + i][16 * tn + r];  // B[o][i] = W2[o][i]
                 }
-                acc = mfma(a, b, acc);
+                acc = mfma32(a, b, acc);
             }
             for (int i = 0; i < 4; ++i) {
                 const float h = bf2f(t.h1[4 * q + i][16 * tn + r]);
