@@ -131,10 +131,13 @@ def certificate_check(g, h, core, rnd, count, seed=3):
     rng = np.random.default_rng(seed)
     cand = np.flatnonzero(g.degrees() > 0).astype(np.uint32)
     verts = rng.choice(cand, size=min(count, cand.size), replace=False).astype(np.uint32)
+    threads = oracle.host_threads()
+    if os.environ.get("OMP_NUM_THREADS", "").isdigit():
+        threads = max(1, min(threads, int(os.environ["OMP_NUM_THREADS"])))
     t = time.perf_counter()
-    fail = oracle.certificate(g, h, core, rnd, verts)
+    fail = oracle.certificate(g, h, core, rnd, verts, threads=threads)
     return {"vertices": int(verts.size), "violations": [int(x) for x in fail],
-            "cpu_s": round(time.perf_counter() - t, 1)}
+            "cpu_s": round(time.perf_counter() - t, 1), "threads": threads}
 
 
 def decomposition(ctx, g, desc, h, log, tune=False, cert=300):
@@ -169,7 +172,8 @@ def decomposition(ctx, g, desc, h, log, tune=False, cert=300):
     r = rnd.cpu().numpy().view(np.uint32)
     setting = ("autotuned: W={}, {} waves/CU".format(tuned["width_words"], tuned["waves_per_cu"]) if tuned
                else "W=32, 16 waves/CU")
-    out = {"workload": f"khcore_decompose, {desc}, h={h}, bounded schedule, host-driven rounds, {setting}",
+    out = {"workload": f"khcore_decompose, {desc}, h={h}, bounded schedule with decremented (h-1)-degree bounds "
+                       f"(KHC_OPT_SCHEDULE 3), host-driven rounds, {setting}",
            "n": g.n, "edges": g.num_edges, "wall_s": round(wall, 3), "rounds": st["rounds"],
            "h_recomputes": st["h_recomputes"], "hm1_recomputes": st["hm1_recomputes"],
            "max_core": int(c.max())}
@@ -276,6 +280,8 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--decompose-scale", type=int, default=20,
                     help="R-MAT scale of the timed decomposition (0: skip; 20: the benchmark graph itself)")
+    ap.add_argument("--decompose-h", default="3,4",
+                    help="h values of the timed decompositions (the --h one is reported as 'decomposition')")
     ap.add_argument("--cert", type=int, default=300,
                     help="sampled vertices of the decomposition's certificate check (0: skip)")
     ap.add_argument("--tune", action="store_true",
@@ -396,10 +402,12 @@ def main():
             ef = 16 if args.decompose_scale >= 20 else 8
             dg, desc = synth.rmat(args.decompose_scale, ef, seed=1), f"R-MAT scale {args.decompose_scale} " \
                                                                      f"(ef {ef}, seed 1)"
-        log(f"timing the decomposition of {desc} at h={h} ...")
-        result["decomposition"] = decomposition(ctx, dg, desc, h, log, tune=args.tune, cert=args.cert)
-        cert = result["decomposition"].get("certificate")
-        bad |= bool(cert and any(cert["violations"]))
+        for dh in [int(x) for x in args.decompose_h.split(",") if x]:
+            log(f"timing the decomposition of {desc} at h={dh} ...")
+            key = "decomposition" if dh == h else f"decomposition_h{dh}"
+            result[key] = decomposition(ctx, dg, desc, dh, log, tune=args.tune, cert=args.cert)
+            cert = result[key].get("certificate")
+            bad |= bool(cert and any(cert["violations"]))
     if args.batched:
         log(f"timing the batched decomposition of {args.batched} graphs ...")
         result["batched"] = batched(ctx, args.batched, h, log)

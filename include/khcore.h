@@ -82,9 +82,12 @@ const char *khc_last_error(const khc_ctx *ctx);
 
 /* Options (khc_set_option).  Values are validated; unknown ids: KHC_EINVAL. */
 #define KHC_OPT_MAX_WIDTH 1       /* max uint64 words per vertex per BFS batch (1..32, pow2; default 32) */
-#define KHC_OPT_SCHEDULE 2        /* 0 = plain recompute of the affected set, 1 = bounded (default),
-                                     2 = local update inside N^h[P] when it is the cheaper of the two
-                                     (host-driven rounds; the persistent driver treats 2 as 0)       */
+#define KHC_OPT_SCHEDULE 2        /* 0 = plain recompute of the affected set, 1 = bounded,
+                                     2 = local update inside N^h[P] when it is the cheaper of the two,
+                                     3 = bounded with the (h-1)-degree bounds lowered by the
+                                     decrement bound instead of recomputed, and refreshed with every
+                                     h-degree recompute (default) (host-driven rounds; the
+                                     persistent driver treats 2 as 0 and 3 as 1)                      */
 #define KHC_OPT_WORKSPACE_LIMIT 3 /* cap on workspace bytes (0 = none)                                  */
 #define KHC_OPT_VALIDATE 4        /* 1 = validate the CSR in khc_graph_create (default 1)               */
 #define KHC_OPT_WAVES_PER_CU 5    /* wavefronts per CU for the BFS level kernels (4..32; default 16)     */
@@ -233,11 +236,14 @@ int khdeg_scanned_arcs(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, u
  * h-degree is at most the level k = max(k, min live h-degree), gives it
  * core k, and recomputes the h-degree of the live vertices within h hops
  * of the removed ones (Algorithms 1-2, Observations 1-2).  The bounded
- * schedule (KHC_OPT_SCHEDULE 1, default) recomputes such a vertex only when
+ * schedules (KHC_OPT_SCHEDULE 1, and 3, the default) recompute such a vertex only when
  * its lower bounds reach the level.  The bounds are structural ((h-1)-degrees
  * of it and its neighbours, after h-LB of Section III) and a decrement bound
  * (a vertex at distance j from the removed set loses at most the vertices
- * within h - j hops of that set).  Both schedules give identical results.
+ * within h - j hops of that set).  Schedule 1 recomputes the (h-1)-degrees
+ * near each removed set; schedule 3 lowers them by the same decrement bound
+ * and refreshes them with every h-degree recompute.  All schedules give
+ * identical results.
  *   h           1..1024 (1..32 with the persistent driver and for graphs
  *               made by khc_graph_create_batched); otherwise KHC_EINVAL
  *   core        device uint32[n] output (isolated vertices: 0)
@@ -388,7 +394,8 @@ int khc_gate_features(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, ui
 
 /* Gated (k,h)-core decomposition: the bounded schedule of khcore_decompose
  * (host-driven rounds, Algorithms 1-2 in level-synchronous form) with a
- * learned gate in front of its recomputes.  A dirty vertex whose exact
+ * learned gate in front of its recomputes (schedule 3 when KHC_OPT_SCHEDULE
+ * is 3, else 1).  A dirty vertex whose exact
  * lower bound lb reached the level k (its stale h-degree d still above k)
  * is first estimated: e = clamp(expm1(8 y), lb, d) with y the network's
  * output on khc_gate_features; if lb + floor((e - lb) * (1 - margin)) > k

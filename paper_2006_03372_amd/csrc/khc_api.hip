@@ -360,7 +360,7 @@ int khc_set_option(khc_ctx *ctx, int option, int64_t value) {
             ctx->max_width = (int)value;
             return KHC_OK;
         case KHC_OPT_SCHEDULE:
-            if (value < 0 || value > 2) return set_error(ctx, KHC_EINVAL, "schedule must be 0, 1 or 2");
+            if (value < 0 || value > 3) return set_error(ctx, KHC_EINVAL, "schedule must be 0, 1, 2 or 3");
             ctx->schedule = (int)value;
             return KHC_OK;
         case KHC_OPT_WORKSPACE_LIMIT:

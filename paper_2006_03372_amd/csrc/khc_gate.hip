@@ -197,8 +197,9 @@ extern "C" int khcore_decompose_gated(khc_ctx *ctx, const khc_graph *g, uint32_t
     if (g->ngraphs > 1) return set_error(ctx, KHC_EINVAL, "the gated mode takes one graph");
     if (!(margin >= 0.f && margin <= 1.f)) return set_error(ctx, KHC_EINVAL, "margin must be in [0, 1]");
     (void)hipSetDevice(ctx->device);
+    // the gate sits in the bounded schedules (1, or 3 with decremented (h-1)-bounds)
     const int saved = ctx->schedule;
-    ctx->schedule = 1;
+    ctx->schedule = saved == 3 ? 3 : 1;
     const GateArgs gate{mlp, margin};
     const int rc = host_decompose(ctx, g, h, core, peel_round, stats, &gate);
     ctx->schedule = saved;

@@ -58,7 +58,7 @@ struct khc_ctx {
     int sticky = 0;
     // options
     int max_width = 32;
-    int schedule = 1;
+    int schedule = 3;
     uint64_t ws_limit = 0;
     int validate = 1;
     int waves_per_cu = 16;

@@ -35,6 +35,7 @@
 //    attributes to h-LB (Section III) over to set removal.
 #include <chrono>
 #include <cstring>
+#include <vector>
 
 #include "khc_round.h"
 
@@ -177,6 +178,25 @@ __global__ void local_apply_kernel(const uint32_t *queue, const uint32_t *s, int
     }
 }
 
+// Schedule 3: the (h-1)-degree bounds of the vertices within h - 2 hops of
+// P (queue levels 1 .. h-2) drop by the decrement bound instead of being
+// recomputed: a vertex at distance j from P loses at most the vertices
+// within h - 1 - j hops of P from its (h-1)-ball.  (Level h - 1 loses at
+// most |P|, applied by kill_kernel.)
+__global__ void dm_decrement_kernel(const uint32_t *queue, const uint32_t *s, int h, uint32_t *dm) {
+    const uint32_t np = s[R_CNT];
+    uint32_t e = np;
+    for (int j = 1; j + 1 < h; ++j) e += s[R_CNT + j];
+    for (uint32_t i = np + blockIdx.x * blockDim.x + threadIdx.x; i < e; i += gridDim.x * blockDim.x) {
+        uint32_t j = 0, at = s[R_CNT];
+        while (i >= at) at += s[R_CNT + ++j];
+        uint32_t loss = 0;
+        for (int r = 0; r <= h - 1 - (int)j; ++r) loss += s[R_CNT + r];
+        const uint32_t u = queue[i];
+        dm[u] = dm[u] > loss ? dm[u] - loss : 0u;
+    }
+}
+
 struct PeelState {
     uint8_t *alive, *dirty;
     uint32_t *d, *dm, *lb, *lbx, *mark, *queue, *list, *s, *part;
@@ -225,7 +245,9 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     const uint32_t n = g->n;
     hipStream_t st = ctx->stream;
     const bool gated = gate && gate->mlp && h >= 2;
-    const bool bounded = (ctx->schedule == 1 || gated) && h >= 2;
+    // schedule 3: (h-1)-degree bounds by decrement, refreshed with every recompute
+    const bool lazy = ctx->schedule == 3 && h >= 2;
+    const bool bounded = (ctx->schedule == 1 || gated || lazy) && h >= 2;
     // schedule 2: each round updates the affected h-degrees inside the
     // region N^h[P] (Section IV-A's update, for a removed set) when that is
     // cheaper than recomputing them
@@ -338,7 +360,16 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
                 rlist = gate_list;
                 rcount = p.s + R_GKEEP;
             }
-            if ((rc = msbfs_degrees(ctx, g, p.alive, h, rlist, rcnt, nullptr, 1, p.d))) return rc;
+            if (lazy) {
+                // the same BFS gives the exact (h-1)-degrees at its level h - 1
+                std::vector<uint32_t *> lv(h, nullptr);
+                lv[h - 2] = p.dm;
+                lv[h - 1] = p.d;
+                if ((rc = msbfs_all_levels(ctx, g, p.alive, h, rlist, rcnt, lv.data()))) return rc;
+                st_local.hm1_recomputes += rcnt;
+            } else if ((rc = msbfs_degrees(ctx, g, p.alive, h, rlist, rcnt, nullptr, 1, p.d))) {
+                return rc;
+            }
             hipLaunchKernelGGL(set_flag_kernel, dim3(grid_n), dim3(256), 0, st, rlist, rcount, p.dirty, (uint8_t)0);
             st_local.h_recomputes += rcnt;
         }
@@ -378,7 +409,9 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         } else {
             // (h-1)-degree bounds change only within h-1 hops of P: recomputed
             // exactly within h-2 hops; the ring at h-1 lost at most |P| (kill)
-            if (e_hm2 > np) {
+            if (e_hm2 > np && lazy) {
+                hipLaunchKernelGGL(dm_decrement_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, (int)h, p.dm);
+            } else if (e_hm2 > np) {
                 if ((rc = msbfs_degrees(ctx, g, p.alive, h - 1, p.queue + np, e_hm2 - np, nullptr, 1, p.dm)))
                     return rc;
                 st_local.hm1_recomputes += e_hm2 - np;

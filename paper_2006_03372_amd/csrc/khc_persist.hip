@@ -896,7 +896,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     const auto t0 = std::chrono::steady_clock::now();
     const uint32_t n = g->n;
     const int W = ctx->persist_width;
-    const bool bounded = ctx->schedule == 1 && h >= 2;
+    const bool bounded = (ctx->schedule == 1 || ctx->schedule == 3) && h >= 2;
     const uint32_t levels_max = h;
     const uint32_t nq = levels_max + 1;
     const size_t words = (size_t)n * W;

@@ -12,9 +12,10 @@ schedule).  Every run prints one JSON line.
 
     python -m paper_2006_03372_amd.sweep --rmat 16,18,20,22 --chung-lu 100000,400000 --h 2,3
 
-With --schedules it instead times one exact decomposition per schedule
-(KHC_OPT_SCHEDULE 1 bounded, 2 local update, 0 plain; plain at h = 2 only)
-of every graph and h, and checks that all schedules give the same cores.
+With --schedules LIST it instead times one exact decomposition per listed
+schedule (KHC_OPT_SCHEDULE 1 bounded, 2 local update, 0 plain, 3 bounded
+with decremented (h-1)-degree bounds; plain at h = 2 only) of every graph
+and h, and checks that all schedules give the same cores.
 """
 from __future__ import annotations
 
@@ -60,25 +61,28 @@ def measure(ctx, g, desc, h, steps, decompose):
     return out
 
 
-def schedules(ctx, g, desc, h):
+def schedules(ctx, g, desc, h, order=(1, 2, 0)):
     import torch
     from . import khcore
     gr = ctx.graph(g)
     ref = None
-    for sched in (1, 2, 0):
+    for sched in order:
         if sched == 0 and h >= 3:
             continue
         ctx.set_option(khcore.OPT_SCHEDULE, sched)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        ctx.set_progress(lambda r, removed, level: _log(f"  schedule {sched}: {time.perf_counter() - t0:.0f} s, "
+                                                        f"round {r}, {removed} removed, level {level}"), 20000)
         core, _, st = ctx.core(gr, h)
         torch.cuda.synchronize()
+        ctx.set_progress(None)
         t = time.perf_counter() - t0
         c = core.cpu().numpy()
         ref = c if ref is None else ref
         print(json.dumps({"graph": desc, "h": h, "schedule": sched, "s": round(t, 3), "rounds": st["rounds"],
                           "local_rounds": st["local_rounds"], "h_recomputes": st["h_recomputes"],
-                          "same": bool((c == ref).all())}), flush=True)
+                          "hm1_recomputes": st["hm1_recomputes"], "same": bool((c == ref).all())}), flush=True)
     ctx.set_option(khcore.OPT_SCHEDULE, 1)
     gr.close()
 
@@ -89,7 +93,7 @@ def main():
     ap.add_argument("--rmat", default="16,18,20", help="R-MAT scales")
     ap.add_argument("--chung-lu", default="", help="Chung-Lu sizes")
     ap.add_argument("--chung-lu-mean", type=float, default=10.0)
-    ap.add_argument("--schedules", action="store_true", help="time the decomposition schedules instead")
+    ap.add_argument("--schedules", default="", help="comma list of schedules to time instead, e.g. 1,2,0")
     ap.add_argument("--h", default="2,3")
     ap.add_argument("--steps", type=int, default=3, help="timed khdeg_compute runs (0: decomposition only)")
     ap.add_argument("--decompose-max", type=int, default=400000,
@@ -111,7 +115,7 @@ def main():
         _log(f"{desc}: n={g.n} edges={g.num_edges} ({time.time() - t0:.1f} s)")
         for h in [int(x) for x in a.h.split(",")]:
             if a.schedules:
-                schedules(ctx, g, desc, h)
+                schedules(ctx, g, desc, h, tuple(int(x) for x in a.schedules.split(",")))
                 continue
             limit = a.decompose_max if h <= 2 else a.decompose_max // 4
             res = measure(ctx, g, desc, h, a.steps, live <= limit)

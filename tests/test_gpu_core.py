@@ -41,7 +41,7 @@ def _gpu_core(ctx, g, h, schedule=1, width=16, driver=1):
     return out
 
 
-def _check(ctx, g, h, schedules=(0, 1), widths=(16,), drivers=(0, 1)):
+def _check(ctx, g, h, schedules=(0, 1, 3), widths=(16,), drivers=(0, 1)):
     c_ref, r_ref = oracle.peel(g, h)
     for drv in drivers:
         for s in schedules:
