@@ -53,8 +53,11 @@ def measure(ctx, g, desc, h, steps, decompose):
     if decompose:
         torch.cuda.synchronize()
         t0 = time.perf_counter()
+        ctx.set_progress(lambda r, removed, level: _log(f"  {desc} h={h}: {time.perf_counter() - t0:.0f} s, "
+                                                        f"round {r}, {removed} removed"), 20000)
         core, _, st = ctx.core(gr, h)
         torch.cuda.synchronize()
+        ctx.set_progress(None)
         out.update({"decompose_s": round(time.perf_counter() - t0, 3), "rounds": st["rounds"],
                     "max_core": int(core.max().item()), "h_recomputes": st["h_recomputes"]})
     gr.close()
