@@ -197,6 +197,16 @@ __global__ void dm_decrement_kernel(const uint32_t *queue, const uint32_t *s, in
     }
 }
 
+// Keep the round's removed and affected counts where the next cleaning
+// readback finds them (the level counters are cleared before it).
+__global__ void round_tally_kernel(uint32_t *s, int h) {
+    if (blockIdx.x || threadIdx.x) return;
+    uint32_t na = 0;
+    for (int j = 1; j <= h; ++j) na += s[R_CNT + j];
+    s[R_PNP] = s[R_CNT];
+    s[R_PNA] = na;
+}
+
 struct PeelState {
     uint8_t *alive, *dirty;
     uint32_t *d, *dm, *lb, *lbx, *mark, *queue, *list, *s, *part;
@@ -206,9 +216,9 @@ struct PeelState {
 };
 
 // Select P, find the vertices within h hops of P before removal, remove P,
-// read back the round counters.
+// and (readback) read back the round counters.
 int peel_round_common(khc_ctx *ctx, const khc_graph *g, uint32_t h, const PeelState &p, bool bounded, uint32_t r,
-                      uint32_t *core, uint32_t *peel_round, int grid_n) {
+                      uint32_t *core, uint32_t *peel_round, int grid_n, bool readback) {
     hipStream_t st = ctx->stream;
     const uint32_t n = g->n;
     hipLaunchKernelGGL(select_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, g->row_ptr, p.alive,
@@ -221,6 +231,7 @@ int peel_round_common(khc_ctx *ctx, const khc_graph *g, uint32_t h, const PeelSt
                            p.items, (int)lev, (int)h);
     hipLaunchKernelGGL(kill_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, p.alive,
                        bounded ? p.dm : (uint32_t *)nullptr, (int)h);
+    if (!readback) return KHC_OK;
     hipError_t e = hipMemcpyAsync(ctx->host_scalars, p.s, (size_t)p.nscal * 4, hipMemcpyDeviceToHost, st);
     if (e == hipSuccess) e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "peel round readback");
@@ -330,8 +341,21 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
     uint32_t r = 0;
     uint32_t *hs = ctx->host_scalars;
     auto last_report = std::chrono::steady_clock::now();
+    // Schedule 3 needs no host value between the removal and the bounds, so
+    // a round does not wait for its counters: the next cleaning readback
+    // brings them (R_PNP, R_PNA, R_LIVE).
+    bool pending = false;
+    auto take_tally = [&]() -> int {
+        pending = false;
+        if (hs[R_PNP] == 0) return set_error(ctx, KHC_ELIMIT, "round removed no vertex");
+        st_local.affected_total += hs[R_PNA];
+        left = hs[R_LIVE];
+        report_progress(ctx, &last_report, r, (uint64_t)n - left, hs[R_K]);
+        return KHC_OK;
+    };
     while (left > 0 && !(ctx->round_limit && r >= ctx->round_limit)) {
         if ((uint64_t)r > (uint64_t)n) return set_error(ctx, KHC_ELIMIT, "more rounds than vertices");
+        bool done = false;
         for (;;) {
             hipLaunchKernelGGL(keymin_kernel, dim3(kMinBlocks), dim3(256), 0, st, n, p.alive,
                                bounded ? p.dirty : (const uint8_t *)nullptr, p.d, p.lb, p.part, p.s, p.s64, (int)h);
@@ -342,6 +366,11 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
             hipError_t e = hipMemcpyAsync(hs, p.s, (size_t)R_CNT * 4, hipMemcpyDeviceToHost, st);
             if (e == hipSuccess) e = hipStreamSynchronize(st);
             if (e != hipSuccess) return check_hip(ctx, e, "level readback");
+            if (pending && (rc = take_tally())) return rc;
+            if (lazy && hs[R_LIVE] == 0) {
+                done = true;
+                break;
+            }
             const uint32_t rn = hs[R_RN];
             if (rn == 0) break;
             const uint32_t *rlist = p.list, *rcount = p.s + R_RN;
@@ -373,7 +402,21 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
             hipLaunchKernelGGL(set_flag_kernel, dim3(grid_n), dim3(256), 0, st, rlist, rcount, p.dirty, (uint8_t)0);
             st_local.h_recomputes += rcnt;
         }
-        if ((rc = peel_round_common(ctx, g, h, p, bounded, r, core, peel_round, grid_n))) return rc;
+        if (done) break;
+        if ((rc = peel_round_common(ctx, g, h, p, bounded, r, core, peel_round, grid_n, !lazy))) return rc;
+        if (lazy) {
+            // every range below comes from the device counters
+            hipLaunchKernelGGL(dm_decrement_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, (int)h, p.dm);
+            hipLaunchKernelGGL(lower_bound_kernel, dim3(wgrid), dim3(256), 0, st, p.queue, p.s, (int)h, n,
+                               g->row_ptr, g->col, p.alive, p.dm, p.lb, (const uint8_t *)p.dirty,
+                               (const uint32_t *)p.d, p.lbx);
+            hipLaunchKernelGGL(finish_kernel, dim3(grid_n), dim3(256), 0, st, p.queue, p.s, (int)h, p.mark, p.dirty,
+                               (uint8_t)1);
+            hipLaunchKernelGGL(round_tally_kernel, dim3(1), dim3(64), 0, st, p.s, (int)h);
+            pending = true;
+            ++r;
+            continue;
+        }
         const uint32_t np = hs[R_CNT];
         uint32_t e_hm2 = 0, e_h = 0;
         for (uint32_t j = 0; j <= h; ++j) {
@@ -428,6 +471,13 @@ int khc::host_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t *
         left -= np;
         ++r;
         report_progress(ctx, &last_report, r, (uint64_t)n - left, hs[R_K]);
+    }
+    if (pending) {
+        // stopped by the round limit: read the last round's counters
+        hipError_t e = hipMemcpyAsync(hs, p.s, (size_t)R_CNT * 4, hipMemcpyDeviceToHost, st);
+        if (e == hipSuccess) e = hipStreamSynchronize(st);
+        if (e != hipSuccess) return check_hip(ctx, e, "last round readback");
+        if ((rc = take_tally())) return rc;
     }
     hipError_t e = hipStreamSynchronize(st);
     if (e != hipSuccess) return check_hip(ctx, e, "peel end");

@@ -9,7 +9,9 @@
 // Round scalars (u32 array s): s[R_K] level, s[R_KNEW] level of this round,
 // s[R_RN] recompute count, s[R_LIVE] live vertices, s[R_SMIN] (sampling
 // mode) nearest queue level holding a sampled vertex, s[R_GKEEP] (learned
-// gate) recomputes kept by the gate, s[R_CNT + j] vertices put
+// gate) recomputes kept by the gate, s[R_PNP] / s[R_PNA] the removed and
+// affected counts of the last round (kept for a later readback),
+// s[R_CNT + j] vertices put
 // on the queue at BFS level j (level 0 = P), s[R_CNT + h + 1 + j] push items
 // of level j; u64 array s64[j]: total degree of the level-j vertices.
 // queue = [P | level 1 | ... | level h]; a queued row with more than
@@ -27,7 +29,7 @@ namespace rnd {
 namespace {  // each including source gets its own copy of the kernels
 
 constexpr int kMinBlocks = 1024;
-enum : int { R_K = 0, R_KNEW = 1, R_RN = 2, R_LIVE = 3, R_SMIN = 4, R_GKEEP = 5, R_CNT = 8 };
+enum : int { R_K = 0, R_KNEW = 1, R_RN = 2, R_LIVE = 3, R_SMIN = 4, R_GKEEP = 5, R_PNP = 6, R_PNA = 7, R_CNT = 8 };
 constexpr uint32_t kPushArcs = 256;  // arcs per push item
 
 inline int round_nscal(uint32_t h) { return R_CNT + 2 * (int)h + 3; }
