@@ -392,6 +392,24 @@ int khcore_decompose_approx(khc_ctx *ctx, const khc_graph *g, uint32_t h, const 
 int khc_gate_features(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h, const uint32_t *dm,
                       float *X);
 
+/* Training samples for the network from one peeling state G(alive): the
+ * features of every live vertex (kind 0: khc_features, for
+ * khcore_decompose_approx; kind 1: khc_gate_features from exact
+ * (h-1)-degrees, for khcore_decompose_gated) and the target
+ * log1p(d^h(v)) / 8 with d^h the exact h-degree, compacted to the live
+ * vertices in vertex order.
+ *   X       device float[n][8] output; rows [0, *count) are written
+ *   target  device float[n] output; entries [0, *count)
+ *   count   host uint32 output: the number of live vertices
+ * 2 <= h <= 64.  Synchronous (reads back the count). */
+int khc_mlp_samples(khc_ctx *ctx, const khc_graph *g, const uint8_t *alive, uint32_t h, int kind, float *X,
+                    float *target, uint32_t *count);
+
+/* Peeling state after round r0 of an exact decomposition: alive[v] = 1 iff
+ * round[v] >= r0, with round the peel_round output of khcore_decompose
+ * (device uint32[n]); alive is device uint8[n].  Asynchronous. */
+int khc_alive_after(khc_ctx *ctx, uint32_t n, const uint32_t *round, uint32_t r0, uint8_t *alive);
+
 /* Gated (k,h)-core decomposition: the bounded schedule of khcore_decompose
  * (host-driven rounds, Algorithms 1-2 in level-synchronous form) with a
  * learned gate in front of its recomputes (schedule 3 when KHC_OPT_SCHEDULE

@@ -13,7 +13,8 @@ OBJDIR = os.path.join(PKG, "_build")
 LIB = os.path.join(PKG, "libkhcore.so")
 
 SOURCES = ["khc_api.hip", "khc_bfs.hip", "khc_peel.hip", "khc_persist.hip", "khc_mlp.hip", "khc_approx.hip", "khc_tune.hip",
-           "khc_noalloc.hip", "khc_sample.hip", "khc_gate.hip"]
+           "khc_noalloc.hip", "khc_sample.hip", "khc_gate.hip",
+           "khc_samples.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

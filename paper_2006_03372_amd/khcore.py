@@ -45,7 +45,7 @@ EXPORTED = [
     "khc_mlp_forward", "khc_mlp_gradient", "khc_mlp_train", "khc_features", "khcore_decompose_approx",
     "khc_persist_profile_read", "khc_set_progress", "khc_autotune", "khc_mlp_save", "khc_mlp_load",
     "khc_mlp_get_moments", "khdeg_compute_noalloc", "khcore_decompose_sampled", "khc_gate_features",
-    "khcore_decompose_gated",
+    "khcore_decompose_gated", "khc_mlp_samples", "khc_alive_after",
 ]
 
 PROGRESS_FN = ctypes.CFUNCTYPE(None, ctypes.c_void_p, ctypes.c_uint32, ctypes.c_uint64, ctypes.c_uint32)
@@ -148,6 +148,8 @@ def load_library(path: str = LIB_PATH):
         "khcore_decompose_approx": ([P, P, u32, P, P, P, ctypes.POINTER(Stats)], i32),
         "khcore_decompose_sampled": ([P, P, u32, P, P, P, ctypes.POINTER(Stats)], i32),
         "khc_gate_features": ([P, P, P, u32, P, P], i32),
+        "khc_mlp_samples": ([P, P, P, u32, i32, P, P, ctypes.POINTER(u32)], i32),
+        "khc_alive_after": ([P, u32, P, u32, P], i32),
         "khcore_decompose_gated": ([P, P, u32, P, ctypes.c_float, P, P, ctypes.POINTER(Stats)], i32),
         "khc_persist_profile_read": ([P, P, P, i32], i32),
         "khc_set_progress": ([P, PROGRESS_FN, P, u32], i32),
@@ -302,6 +304,25 @@ class Context:
         X = torch.empty((graph.n, 8), dtype=torch.float32, device=graph.device)
         self._check(self.lib.khc_gate_features(self.handle, graph.handle, _dptr(alive), h, _dptr(dm), _dptr(X)))
         return X
+
+    def mlp_samples(self, graph: "Graph", h: int, alive=None, kind: int = 0):
+        """(X float32 [m, 8], target float32 [m]) of the m live vertices of
+        G(alive): features (kind 0 estimating mode, 1 gate) and
+        log1p(d^h) / 8, computed and compacted on the device."""
+        torch = _torch()
+        X = torch.empty((graph.n, 8), dtype=torch.float32, device=graph.device)
+        t = torch.empty(graph.n, dtype=torch.float32, device=graph.device)
+        m = ctypes.c_uint32(0)
+        self._check(self.lib.khc_mlp_samples(self.handle, graph.handle, _dptr(alive), h, int(kind), _dptr(X),
+                                             _dptr(t), ctypes.byref(m)))
+        return X[:m.value], t[:m.value]
+
+    def alive_after(self, rnd, r0: int):
+        """uint8 mask of the vertices whose removal round (device tensor) is >= r0."""
+        torch = _torch()
+        out = torch.empty(rnd.numel(), dtype=torch.uint8, device=rnd.device)
+        self._check(self.lib.khc_alive_after(self.handle, rnd.numel(), _dptr(rnd), int(r0), _dptr(out)))
+        return out
 
     def core_gated(self, graph: "Graph", h: int, mlp=None, margin: float = 0.0, with_round: bool = False):
         """Bounded-schedule decomposition with the learned recompute gate:

@@ -2,11 +2,11 @@
 
 Training samples come from the method itself: for each training graph the
 exact GPU peeling gives, for every vertex, the round it is removed in; the
-graph induced by the vertices still present after round r is a state the
-approximate driver will meet.  For several such states the library computes
-the eight features (khc_features) and the exact h-degrees (khdeg_compute),
-which are the regression targets log1p(d^h) / 8.  Training runs on the GPU
-(khc_mlp_train).  Accuracy is judged against exact core numbers: the
+graph induced by the vertices still present after round r (khc_alive_after)
+is a state the approximate driver will meet.  For several such states the
+library computes, on the device, the eight features of every live vertex
+and the regression target log1p(d^h) / 8 from its exact h-degree
+(khc_mlp_samples).  Training runs on the GPU (khc_mlp_train).  Accuracy is judged against exact core numbers: the
 fraction of vertices with the exact core, the mean absolute error, and the
 precision of the paper's Section V (Exp-4), 1 - mean over v of
 |c(v) - c^(v)| / c(v), taken over vertices whose exact core is not 0.
@@ -32,41 +32,25 @@ def _torch():
 def states_of(ctx, gr, h, fractions=(0.0, 0.2, 0.4, 0.6, 0.8)):
     """Alive masks (device uint8) after the given fractions of the exact
     peeling rounds, plus the exact decomposition (core, round)."""
-    torch = _torch()
     core, rnd, st = ctx.core(gr, h, with_round=True)
     rounds = int(st["rounds"])
-    r = rnd.view(torch.int32)
-    masks = []
-    for f in fractions:
-        r0 = int(f * rounds)
-        masks.append((r >= r0).to(torch.uint8))
+    masks = [ctx.alive_after(rnd, int(f * rounds)) for f in fractions]
     return masks, core, rnd
 
 
 def samples(ctx, gr, h, masks):
-    """Features and targets of the live vertices of every state."""
+    """Features and targets of the live vertices of every state (built by
+    khc_mlp_samples on the device)."""
     torch = _torch()
-    xs, ts = [], []
-    for m in masks:
-        X, _, _ = ctx.features(gr, h, m)
-        d = ctx.hdeg(gr, h, m)
-        live = m.bool()
-        xs.append(X[live])
-        ts.append(torch.log1p(d[live].double()).float() / FEATURE_SCALE)
+    xs, ts = zip(*(ctx.mlp_samples(gr, h, m, kind=0) for m in masks))
     return torch.cat(xs), torch.cat(ts)
 
 
 def gate_samples(ctx, gr, h, masks):
-    """Gate features and targets of the live vertices of every state."""
+    """Gate features and targets of the live vertices of every state (built
+    by khc_mlp_samples on the device)."""
     torch = _torch()
-    xs, ts = [], []
-    for m in masks:
-        dm = ctx.hdeg(gr, h - 1, m)
-        X = ctx.gate_features(gr, h, dm, m)
-        d = ctx.hdeg(gr, h, m)
-        live = m.bool()
-        xs.append(X[live])
-        ts.append(torch.log1p(d[live].double()).float() / FEATURE_SCALE)
+    xs, ts = zip(*(ctx.mlp_samples(gr, h, m, kind=1) for m in masks))
     return torch.cat(xs), torch.cat(ts)
 
 

@@ -163,6 +163,34 @@ def test_features_match_oracle(ctx, h):
         assert ub[v] == max(int(lb[v]), int(min(n_live - 1, c.sum())))
 
 
+@pytest.mark.parametrize("kind", [0, 1])
+def test_mlp_samples_match_host(ctx, kind):
+    """khc_mlp_samples: the features of the live vertices in vertex order
+    (rows of khc_features / khc_gate_features) and log1p of the oracle's
+    h-degree over 8; khc_alive_after against numpy."""
+    import torch
+    g = synth.chung_lu(2500, 8.0, 2.5, seed=14)
+    h = 3
+    alive = synth.random_alive(g.n, 0.7, 5)
+    a = torch.from_numpy(alive).cuda()
+    gr = ctx.graph(g)
+    X, t = ctx.mlp_samples(gr, h, a, kind=kind)
+    if kind == 0:
+        Xall, _, _ = ctx.features(gr, h, a)
+    else:
+        dm = oracle.hdeg(g, h - 1, alive).astype(np.uint32)
+        Xall = ctx.gate_features(gr, h, torch.from_numpy(dm.view(np.int32)).cuda(), a)
+    rnd = np.random.default_rng(3).integers(0, 50, size=g.n).astype(np.uint32)
+    got = ctx.alive_after(torch.from_numpy(rnd.view(np.int32)).cuda(), 17).cpu().numpy()
+    gr.close()
+    live = np.flatnonzero(alive)
+    assert X.shape == (live.size, 8) and t.shape == (live.size,)
+    assert np.array_equal(X.cpu().numpy(), Xall.cpu().numpy()[live])
+    d = oracle.hdeg(g, h, alive).astype(np.float64)[live]
+    assert np.allclose(t.cpu().numpy(), (np.log1p(d) / 8.0).astype(np.float32), rtol=2e-7, atol=0)
+    assert np.array_equal(got, (rnd >= 17).astype(np.uint8))
+
+
 def test_bounds_bracket_exact_degree(ctx):
     import torch
     g = synth.rmat(11, 8, seed=6)
