@@ -1,5 +1,6 @@
-"""Benchmark: h-hop degrees of every vertex of R-MAT scale 20 at h = 3, then
-the exact (k,3)-core decomposition of the same graph.
+"""Benchmark: h-hop degrees of every vertex of R-MAT scale 20 at h = 3, the
+exact (k,h)-core decompositions of the same graph, and the learned-mode
+error.
 
 One step = khdeg_compute over all vertices of the graph (every live vertex
 gets its exact h-hop degree by the multi-source bounded BFS kernels).  The
@@ -7,9 +8,14 @@ throughput is in GTEPS: traversed edges, where the work of one vertex is the
 number of arcs a scalar bounded BFS from it examines (khdeg_scanned_arcs),
 divided by the step time, 10^9 per second.
 
+After the timed steps, outside the timed region: the exact (k,h)-core
+decompositions of the same graph at h = 3 and 4 (wall time), and the
+learned-mode error (the estimating mode on R-MAT-18 at h = 4 with a network
+trained on R-MAT-16 graphs, against the exact decomposition).
+
 Parity is checked in the same run, outside the timed region: the last
 step's degrees against the CPU oracle on the sampled vertices the CPU
-baseline computes, and the decomposition's core numbers and removal rounds
+baseline computes, and the decompositions' core numbers and removal rounds
 by the peeling-order certificate on sampled vertices.  A mismatch exits
 with status 1.
 
@@ -183,6 +189,50 @@ def decomposition(ctx, g, desc, h, log, tune=False, cert=300):
     return out
 
 
+def learned_leg(ctx, log, h=4, train_count=32, test_scale=18):
+    """The metric's learned-mode error: the network trained on the exact
+    h-degrees of peeling states of `train_count` R-MAT-16 graphs (seeds
+    101..), then the estimating mode (khcore_decompose_approx) on R-MAT of
+    `test_scale` against the exact decomposition: exact fraction, mean
+    absolute core error, the paper's precision and the speedup."""
+    import numpy as np
+    import torch
+    from paper_2006_03372_amd import khcore, learned, synth
+    ctx.set_option(khcore.OPT_SCHEDULE, 3)
+    ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
+    ctx.set_option(khcore.OPT_WAVES_PER_CU, 16)
+    t0 = time.perf_counter()
+    graphs = [synth.rmat(16, 8, seed=101 + i) for i in range(train_count)]
+    X, t = learned.training_set(ctx, graphs, h)
+    net = ctx.mlp(seed=7)
+    losses = net.train(X, t, epochs=10, batch=4096, lr=2e-3, seed=1)
+    torch.cuda.synchronize()
+    t_train = time.perf_counter() - t0
+    log(f"learned mode: {X.shape[0]} training samples, {t_train:.0f} s")
+    del X, t
+    ef = 16 if test_scale >= 20 else 8
+    g = synth.rmat(test_scale, ef, seed=1)
+    gr = ctx.graph(g)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    exact, _, _ = ctx.core(gr, h)
+    torch.cuda.synchronize()
+    t_exact = time.perf_counter() - t0
+    t0 = time.perf_counter()
+    approx, _, st = ctx.core_approx(gr, h, net)
+    torch.cuda.synchronize()
+    t_approx = time.perf_counter() - t0
+    gr.close()
+    net.close()
+    acc = learned.accuracy(exact.cpu().numpy().view(np.uint32), approx.cpu().numpy().view(np.uint32))
+    return {"workload": f"khcore_decompose_approx, R-MAT scale {test_scale} (ef {ef}, seed 1), h={h}; network "
+                        f"trained on {train_count} R-MAT scale 16 graphs (seeds 101..{100 + train_count})",
+            "exact_fraction": round(acc["exact_fraction"], 5), "mae": round(acc["mae"], 3),
+            "precision": round(acc["precision"], 6), "approx_s": round(t_approx, 2),
+            "exact_s": round(t_exact, 2), "speedup_vs_exact": round(t_exact / t_approx, 3),
+            "train_s": round(t_train, 1), "loss_last": float(losses[-1])}
+
+
 def batched(ctx, count, h, log):
     """Batched decomposition of `count` Chung-Lu graphs (the first of the
     256-graph batch: n ~ U{500..20000}, mean degree ~ U[4,16], beta 2.5,
@@ -280,6 +330,7 @@ def main():
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--decompose-scale", type=int, default=20,
                     help="R-MAT scale of the timed decomposition (0: skip; 20: the benchmark graph itself)")
+    ap.add_argument("--no-learned", action="store_true", help="skip the learned-mode error leg")
     ap.add_argument("--decompose-h", default="3,4",
                     help="h values of the timed decompositions (the --h one is reported as 'decomposition')")
     ap.add_argument("--cert", type=int, default=300,
@@ -310,6 +361,7 @@ def main():
         return calibrate("gather", args.calibrate_gather)
     if args.profile_pass:
         args.warmup, args.steps, args.no_cpu, args.decompose_scale = 0, 1, True, 0
+        args.no_learned = True
 
     t = time.time()
     g = synth.rmat(args.scale, args.edge_factor, seed=1)
@@ -408,6 +460,9 @@ def main():
             result[key] = decomposition(ctx, dg, desc, dh, log, tune=args.tune, cert=args.cert)
             cert = result[key].get("certificate")
             bad |= bool(cert and any(cert["violations"]))
+    if not args.no_learned:
+        log("learned mode: training, then the estimating decomposition against exact ...")
+        result["learned_mode"] = learned_leg(ctx, log)
     if args.batched:
         log(f"timing the batched decomposition of {args.batched} graphs ...")
         result["batched"] = batched(ctx, args.batched, h, log)
