@@ -86,8 +86,8 @@ const char *khc_last_error(const khc_ctx *ctx);
                                      2 = local update inside N^h[P] when it is the cheaper of the two,
                                      3 = bounded with the (h-1)-degree bounds lowered by the
                                      decrement bound instead of recomputed, and refreshed with every
-                                     h-degree recompute (default) (host-driven rounds; the
-                                     persistent driver treats 2 as 0 and 3 as 1)                      */
+                                     h-degree recompute (default) (the persistent driver treats
+                                     2 as 0)                                                          */
 #define KHC_OPT_WORKSPACE_LIMIT 3 /* cap on workspace bytes (0 = none)                                  */
 #define KHC_OPT_VALIDATE 4        /* 1 = validate the CSR in khc_graph_create (default 1)               */
 #define KHC_OPT_WAVES_PER_CU 5    /* wavefronts per CU for the BFS level kernels (4..32; default 16)     */

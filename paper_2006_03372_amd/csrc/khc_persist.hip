@@ -10,12 +10,16 @@
 // flag that every workgroup checks, so the kernel always exits.  The launch
 // is captured once in a hipGraph and replayed.
 //
-// The algorithm is the bounded schedule of khc_peel.hip (or the plain one):
+// The algorithm is a bounded schedule of khc_peel.hip (or the plain one):
 // levels k <- max(k, min key), dirty vertices whose lower bound reaches the
 // level are recomputed first, P = {clean live v : d(v) <= k} is removed, the
 // vertices within h hops of P in the graph before removal are found by a
-// push BFS, exact (h-1)-degrees are recomputed within h-1 hops of P, and the
-// vertices within h hops of P become dirty with fresh lower bounds.
+// push BFS, the (h-1)-degrees near P are brought up to date, and the
+// vertices within h hops of P become dirty with fresh lower bounds.  The
+// (h-1)-degrees of the ring at distance h-1 from P lose |P|; those within
+// h-2 hops of P are recomputed exactly (schedule 1) or lowered by the
+// decrement bound and refreshed whenever the vertex's h-degree is
+// recomputed, from the same BFS (schedule 3).
 //
 // Several graphs can be decomposed together: their disjoint union is one
 // CSR and gid[v] names the graph of v.  Each graph keeps its own level
@@ -102,7 +106,7 @@ struct PParams {
     const uint32_t *gid;  // graph of each vertex (null: one graph)
     uint32_t ngraphs;
     uint32_t h;
-    int bounded;
+    int bounded;  // 0 plain, 1 schedule 1, 2 schedule 3
     uint32_t push_cost;  // push/pull rule of the BFS levels (KHC_OPT_PUSH_COST)
     int profile;  // time the phases (KHC_OPT_PROFILE)
     uint32_t round_limit;  // stop after this many rounds (0: none)
@@ -122,6 +126,7 @@ struct PParams {
     uint64_t *hacc;
     uint32_t *hdone;
     uint32_t *counts;
+    uint32_t *counts2;  // split jobs: the last level's per-lane totals
     uint32_t *bq;   // frontier lists, n entries per level
     uint64_t *bhq;  // push items, hq_len per level
     size_t hq_len;
@@ -442,12 +447,14 @@ static_assert((int)PH_DONE + 1 == KHC_PERSIST_PHASES, "phase count of the profil
 
 // A bounded-BFS job: h-degrees (levels hops) of the n sources grouped by
 // graph in p.list into out[] (clearing their dirty flags when clean is
-// set), then continue with phase ret.
+// set), then continue with phase ret.  A split job also writes the
+// (levels-1)-hop counts into p.dm: its levels add their totals to counts
+// one by one, the last level into counts2.
 struct Job {
     uint32_t n, levels;
     uint32_t *out;
     int ret;
-    bool clean;
+    bool clean, split;
 };
 
 template <int W>
@@ -462,17 +469,17 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
             atomicCAS(p.sync.abort, 0u, (uint32_t)ABORT_PLACEMENT);
     }
     const uint32_t n = p.n, h = p.h;
-    const bool bounded = p.bounded != 0;
+    const bool bounded = p.bounded != 0, lazy = p.bounded == 2;
     PCtl *ctl = p.ctl;
     const uint32_t per = 64u * W;
     const int lane = threadIdx.x & 63;
 
     // uniform control state
     int phase = PH_INIT;
-    Job job{0, 0, nullptr, PH_DONE, false};
+    Job job{0, 0, nullptr, PH_DONE, false, false};
     uint32_t batch = 0, lev = 0, aff_l = 0, np = 0, e_hm2 = 0, e_hm1 = 0, e_h = 0;
-    auto start_job = [&](uint32_t cnt, uint32_t levels, uint32_t *out, int ret, bool clean) {
-        job = Job{cnt, levels, out, ret, clean};
+    auto start_job = [&](uint32_t cnt, uint32_t levels, uint32_t *out, int ret, bool clean, bool split) {
+        job = Job{cnt, levels, out, ret, clean, split};
         batch = 0;
         return cnt ? (int)PH_BFS_RESET : ret;
     };
@@ -570,7 +577,10 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 break;
             case PH_CLEAN:
                 // the job's scatter cleared the recomputed vertices' dirty flags
-                if (gtid() == 0) ctl->stat_hrec += ctl->rn;
+                if (gtid() == 0) {
+                    ctl->stat_hrec += ctl->rn;
+                    if (lazy) ctl->stat_hm1 += ctl->rn;
+                }
                 break;
             case PH_SELECT: {
                 // P: clean live vertices at or below their graph's level
@@ -616,14 +626,18 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 }
                 for (size_t i = gtid(); i < np; i += gstride()) p.alive[p.queue[i]] = 0;
                 if (bounded)
-                    // (h-1)-degree bounds of the ring at distance h-1 from P:
-                    // only P itself can leave their (h-1)-balls
-                    for (size_t i = e_hm2 + gtid(); i < e_hm1; i += gstride()) {
+                    // (h-1)-degree bounds: a vertex at distance j from P loses
+                    // at most the vertices within h-1-j hops of P (P itself
+                    // for the ring at distance h-1); schedule 1 recomputes
+                    // the rings nearer P below instead
+                    for (size_t i = (lazy ? np : e_hm2) + gtid(); i < e_hm1; i += gstride()) {
+                        uint32_t j = 0, at = ctl->acnt[0];
+                        while (i >= at) at += ctl->acnt[++j];
                         const uint32_t u = p.queue[i];
-                        const uint32_t pu = ring_total(p, u, 0);  // |P| of u's graph
-                        p.dm[u] = p.dm[u] > pu ? p.dm[u] - pu : 0u;
+                        const uint32_t loss = ring_total(p, u, (int)h - 1 - (int)j);
+                        p.dm[u] = p.dm[u] > loss ? p.dm[u] - loss : 0u;
                     }
-                {
+                if (!lazy) {
                     // sources of the recompute job, grouped by graph: the
                     // (h-1)-degrees within h-2 hops of P (bounded) or the
                     // h-degrees of the whole affected set (plain)
@@ -644,8 +658,8 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                                            __HIP_MEMORY_SCOPE_SYSTEM);
                     }
                     ctl->stat_aff += e_h - np;
-                    if (bounded) ctl->stat_hm1 += e_hm2 - np;
-                    else ctl->stat_hrec += e_h - np;
+                    if (!bounded) ctl->stat_hrec += e_h - np;
+                    else if (!lazy) ctl->stat_hm1 += e_hm2 - np;
                     if (np == 0) {
                         ctl->abort_reason = 1;
                         atomicExch(p.sync.abort, 1u);
@@ -669,7 +683,7 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                         p.bqdeg[2 * i] = 0;
                         p.bqdeg[2 * i + 1] = 0;
                     }
-                    for (uint32_t i = threadIdx.x; i < per; i += blockDim.x) p.counts[i] = 0;
+                    for (uint32_t i = threadIdx.x; i < per; i += blockDim.x) p.counts[i] = p.counts2[i] = 0;
                     if (threadIdx.x == 0) ctl->stat_batches++;
                     if (batch == 0) scan_segments(p, s_ws);
                 }
@@ -744,8 +758,8 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 lp.hacc = p.hacc;
                 lp.hdone = p.hdone;
                 lp.work = p.bwork + lev;
-                lp.counts = p.counts;
-                lp.count_keep = 1;
+                lp.counts = (job.split && lev == job.levels) ? p.counts2 : p.counts;
+                lp.count_keep = job.split ? 0 : 1;
                 lp.count_first = lev == 1;
                 const BatchRange br = *p.brange;
                 lp.nnz = br.arcs;
@@ -771,7 +785,12 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 const uint32_t cnt = job.n - first < per ? job.n - first : per;
                 for (size_t l = gtid(); l < cnt; l += gstride()) {
                     const uint32_t s = job_source(p, first + (uint32_t)l);
-                    job.out[s] = p.counts[l];
+                    if (job.split) {
+                        job.out[s] = p.counts[l] + p.counts2[l];
+                        p.dm[s] = p.counts[l];
+                    } else {
+                        job.out[s] = p.counts[l];
+                    }
                     if (job.clean) p.dirty[s] = 0;
                 }
                 for (uint32_t j = 0; j <= job.levels; ++j) {
@@ -806,15 +825,15 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
         switch (phase) {
             case PH_INIT: phase = PH_COMPACT; break;
             case PH_COMPACT:
-                phase = start_job(ctl->nsrc, h, p.d, bounded ? (int)PH_LB_ALL : (int)PH_KEYMIN, false);
-                // the (h-1)-degrees follow the h-degrees with the same sources
+                // bounded: the initial (h-1)-degrees come from the same BFS
+                phase = start_job(ctl->nsrc, h, p.d, bounded ? (int)PH_LB_ALL : (int)PH_KEYMIN, false, bounded);
                 break;
             case PH_LB_ALL: phase = ctl->left ? PH_KEYMIN : PH_DONE; break;
             case PH_KEYMIN: phase = PH_LEVEL; break;
             case PH_LEVEL: phase = bounded ? PH_COLLECT : PH_SELECT; break;
             case PH_COLLECT: {
                 const uint32_t rn = ctl->rn;
-                phase = rn ? start_job(rn, h, p.d, PH_CLEAN, true) : (int)PH_SELECT;
+                phase = rn ? start_job(rn, h, p.d, PH_CLEAN, true, lazy) : (int)PH_SELECT;
                 break;
             }
             case PH_CLEAN: phase = PH_KEYMIN; break;
@@ -827,10 +846,12 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 else phase = PH_KILL;
                 break;
             case PH_KILL:
-                if (bounded)
-                    phase = start_job(e_hm2 - np, h - 1, p.dm, PH_LBD, false);
+                if (lazy)
+                    phase = PH_LBD;
+                else if (bounded)
+                    phase = start_job(e_hm2 - np, h - 1, p.dm, PH_LBD, false, false);
                 else
-                    phase = start_job(e_h - np, h, p.d, PH_UNMARK, false);
+                    phase = start_job(e_h - np, h, p.d, PH_UNMARK, false, false);
                 break;
             case PH_LBD:
             case PH_UNMARK:
@@ -849,9 +870,6 @@ __global__ __launch_bounds__(kBlockThreads) void peel_persistent_kernel(PParams 
                 if ((batch + 1) * per < job.n) {
                     ++batch;
                     phase = PH_BFS_RESET;
-                } else if (job.ret == PH_LB_ALL && job.levels == h && bounded) {
-                    // initial h-degrees done: now the initial (h-1)-degrees
-                    phase = start_job(ctl->nsrc, h - 1, p.dm, PH_LB_ALL, false);
                 } else {
                     phase = job.ret;
                     if (phase == PH_KEYMIN && !ctl->left) phase = PH_DONE;
@@ -911,7 +929,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
         (rc = ws_get(ctx, WS_FNZ, (size_t)fnz_words * 3 * 4, &fnz)) ||
         (rc = ws_get(ctx, WS_HACC, ((size_t)g->n_heavy + 1) * W * 8, &hacc)) ||
         (rc = ws_get(ctx, WS_HDONE, ((size_t)g->n_heavy + 1) * 4, &hdone)) ||
-        (rc = ws_get(ctx, WS_COUNTS, (size_t)64 * kMaxWidth * 4, &counts)) ||
+        (rc = ws_get(ctx, WS_COUNTS, (size_t)2 * 64 * kMaxWidth * 4, &counts)) ||
         (rc = ws_get(ctx, WS_BQUEUE, (size_t)nq * n * 4 + 4, &bq)) ||
         (rc = ws_get(ctx, WS_HQUEUE, (size_t)nq * hq_len * 8, &bhq)) ||
         (rc = ws_get(ctx, WS_MISC, (size_t)nq * 32 + 64, &bctr)) ||
@@ -947,7 +965,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.gid = g->gid;
     p.ngraphs = g->ngraphs;
     p.h = h;
-    p.bounded = bounded ? 1 : 0;
+    p.bounded = bounded ? (ctx->schedule == 3 ? 2 : 1) : 0;
     p.profile = ctx->profile ? 1 : 0;
     p.round_limit = ctx->round_limit;
     p.progress = ctx->persist_progress_dev;
@@ -977,6 +995,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     p.hacc = (uint64_t *)hacc;
     p.hdone = (uint32_t *)hdone;
     p.counts = (uint32_t *)counts;
+    p.counts2 = p.counts + 64 * kMaxWidth;
     p.bq = (uint32_t *)bq;
     p.bhq = (uint64_t *)bhq;
     p.hq_len = hq_len;
@@ -1011,7 +1030,7 @@ int persistent_decompose(khc_ctx *ctx, const khc_graph *g, uint32_t h, uint32_t 
     hipStream_t st = ctx->stream;
 
     // one graph per argument set, replayed on later calls
-    khc_ctx::PersistGraph key{g,           h,         W,       grid, bounded ? 1 : 0, p.profile, p.round_limit,
+    khc_ctx::PersistGraph key{g,           h,         W,       grid, p.bounded, p.profile, p.round_limit,
                               core,        peel_round, p.sync.timeout_ticks, (int)p.sync.grouped, p.push_cost,
                               nullptr};
     hipGraphExec_t exec = nullptr;

@@ -49,7 +49,7 @@ def test_batch_matches_oracle_per_graph(ctx, h):
     graphs.append(synth.from_edges(7, [], []))          # isolated vertices only
     graphs.append(synth.cycle(2 * h + 3))               # closed form: all 2h
     graphs.insert(3, synth.complete(9))                 # closed form: all 8
-    for sched in (0, 1):
+    for sched in (0, 1, 3):
         for width in (8, 32):
             print(f"batch h={h} schedule={sched} width={width} graphs={len(graphs)}", flush=True)
             c, r, st, vb = _run(ctx, graphs, h, sched, width)
@@ -76,6 +76,23 @@ def test_batch_equals_single_graph_runs(ctx):
     # deterministic
     c2, r2, _, _ = _run(ctx, graphs, 3)
     assert (c == c2).all() and (r == r2).all()
+
+
+def test_batch_schedule3_matches_schedule1(ctx):
+    """Schedule 3 in the persistent kernel (decremented (h-1)-degree bounds,
+    refreshed by the cleaning BFS) removes the same vertices in the same
+    rounds as schedule 1, and computes (h-1)-degrees only for the vertices
+    whose h-degree it recomputes."""
+    graphs = _graphs(16, 300, 4000, seed=23)
+    for h in (3, 4):
+        print(f"batch schedule 1 vs 3 h={h} graphs={len(graphs)}", flush=True)
+        c1, r1, st1, _ = _run(ctx, graphs, h, 1, 16)
+        c3, r3, st3, _ = _run(ctx, graphs, h, 3, 16)
+        assert (c1 == c3).all() and (r1 == r3).all(), h
+        assert st1["rounds"] == st3["rounds"]
+        # the initial pass computes both degrees of every vertex; later
+        # (h-1)-degrees come only with the cleaning recomputes
+        assert st3["hm1_recomputes"] == st3["h_recomputes"]
 
 
 def test_batch_rejects_foreign_column(ctx):
