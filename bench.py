@@ -347,7 +347,7 @@ def main():
                     help="only gather random 256-byte rows of a MIB MiB table three times (counter calibration)")
     args = ap.parse_args()
     if args.gpus != 1 or int(os.environ.get("WORLD_SIZE", "1")) > 1:
-        print("bench.py runs on one GPU only: this build measures the single-GPU path "
+        print("bench.py runs on one GPU only: it measures the single-GPU path "
               "(--gpus 1); multi-GPU sharding is not implemented.", file=sys.stderr)
         sys.exit(2)
 
