@@ -15,7 +15,8 @@ schedule).  Every run prints one JSON line.
 With --schedules LIST it instead times one exact decomposition per listed
 schedule (KHC_OPT_SCHEDULE 1 bounded, 2 local update, 0 plain, 3 bounded
 with decremented (h-1)-degree bounds; plain at h = 2 only) of every graph
-and h, and checks that all schedules give the same cores.
+and h, and checks that all schedules give the same cores.  --driver 1 runs
+those decompositions in the persistent kernel instead of host-driven rounds.
 """
 from __future__ import annotations
 
@@ -64,7 +65,7 @@ def measure(ctx, g, desc, h, steps, decompose):
     return out
 
 
-def schedules(ctx, g, desc, h, order=(1, 2, 0)):
+def schedules(ctx, g, desc, h, order=(1, 2, 0), driver=0):
     import torch
     from . import khcore
     gr = ctx.graph(g)
@@ -83,7 +84,8 @@ def schedules(ctx, g, desc, h, order=(1, 2, 0)):
         t = time.perf_counter() - t0
         c = core.cpu().numpy()
         ref = c if ref is None else ref
-        print(json.dumps({"graph": desc, "h": h, "schedule": sched, "s": round(t, 3), "rounds": st["rounds"],
+        print(json.dumps({"graph": desc, "h": h, "schedule": sched, "driver": driver,
+                          "s": round(t, 3), "rounds": st["rounds"],
                           "local_rounds": st["local_rounds"], "h_recomputes": st["h_recomputes"],
                           "hm1_recomputes": st["hm1_recomputes"], "same": bool((c == ref).all())}), flush=True)
     ctx.set_option(khcore.OPT_SCHEDULE, 1)
@@ -102,8 +104,11 @@ def main():
     ap.add_argument("--decompose-max", type=int, default=400000,
                     help="decompose graphs with at most this many non-isolated vertices (h=2) "
                          "or a quarter of it (h>=3)")
+    ap.add_argument("--driver", type=int, default=0, choices=(0, 1),
+                    help="with --schedules: 0 host-driven rounds, 1 the persistent kernel")
     a = ap.parse_args()
     ctx = khcore.Context(0)
+    ctx.set_option(khcore.OPT_DRIVER, a.driver)
     graphs = []
     for sc in [int(x) for x in a.rmat.split(",") if x]:
         ef = 16 if sc >= 20 else 8
@@ -118,7 +123,7 @@ def main():
         _log(f"{desc}: n={g.n} edges={g.num_edges} ({time.time() - t0:.1f} s)")
         for h in [int(x) for x in a.h.split(",")]:
             if a.schedules:
-                schedules(ctx, g, desc, h, tuple(int(x) for x in a.schedules.split(",")))
+                schedules(ctx, g, desc, h, tuple(int(x) for x in a.schedules.split(",")), a.driver)
                 continue
             limit = a.decompose_max if h <= 2 else a.decompose_max // 4
             res = measure(ctx, g, desc, h, a.steps, live <= limit)
