@@ -134,3 +134,109 @@ def test_structural_lower_bound(h):
                 assert d[u] >= dm[w]
             if nb:
                 assert d[u] >= max(dm[w] for w in nb)
+
+
+def _simulate_bounded(g, h, lazy):
+    """The bounded peeling schedules on the CPU, step by step as the device
+    rounds take them, with the h- and (h-1)-degrees from the oracle:
+
+    level k <- max(k, min key) (key: the lower bound of a dirty vertex, the
+    h-degree of a clean one); dirty vertices whose bound reached the level
+    and whose stale h-degree is above it are recomputed (lazy: their
+    (h-1)-degrees too) until none is left; P = {v : d(v) <= k} is removed;
+    the (h-1)-degrees of the vertices at distance j <= h - 1 from P drop by
+    the ring sizes within h - 1 - j hops of P (schedule 1 recomputes the
+    rings within h - 2 hops instead); the vertices within h hops of P get
+    the decrement and structural bounds and become dirty.
+
+    Along the way every stored value must stay on its side of the truth:
+    d >= d^h, dm <= d^{h-1}, and lb <= d^h for dirty vertices.  Returns the
+    core numbers and removal rounds."""
+    n = g.n
+    alive = np.ones(n, dtype=np.uint8)
+    d = oracle.hdeg(g, h, alive).astype(np.int64)
+    dm = oracle.hdeg(g, h - 1, alive).astype(np.int64)
+    nbrs = [g.col[g.row_ptr[u]:g.row_ptr[u + 1]] for u in range(n)]
+
+    def structural(u):
+        m = dm[u]
+        for w in nbrs[u]:
+            if alive[w] and dm[w] > m:
+                m = dm[w]
+        return m
+
+    lb = np.array([structural(u) for u in range(n)], dtype=np.int64)
+    lbx = np.zeros(n, dtype=np.int64)
+    dirty = np.zeros(n, dtype=bool)
+    core = np.zeros(n, dtype=np.int64)
+    rnd = np.zeros(n, dtype=np.int64)
+    k, r = 0, 0
+    while alive.any():
+        while True:
+            live = np.flatnonzero(alive)
+            key = np.where(dirty, lb, d)
+            k = max(k, int(key[live].min()))
+            R = [int(v) for v in live if dirty[v] and lb[v] <= k and d[v] > k]
+            if not R:
+                break
+            exact = oracle.hdeg(g, h, alive)
+            exact_m = oracle.hdeg(g, h - 1, alive)
+            for v in R:
+                d[v] = exact[v]
+                dirty[v] = False
+                if lazy:
+                    dm[v] = exact_m[v]
+        P = [int(v) for v in live if d[v] <= k]
+        assert P
+        dist = _dist_from_set(g, alive.astype(bool), P)
+        C = [int(np.sum(dist[live] == t)) for t in range(h + 1)]
+        core[P] = k
+        rnd[P] = r
+        alive[P] = 0
+        affected = [int(u) for u in np.flatnonzero(alive) if dist[u] <= h]
+        for u in affected:
+            j = int(dist[u])
+            if j <= h - 1 and (lazy or j == h - 1):
+                dm[u] = max(0, dm[u] - sum(C[:h - j]))
+        if not lazy:
+            exact_m = oracle.hdeg(g, h - 1, alive)
+            for u in affected:
+                if dist[u] <= h - 2:
+                    dm[u] = exact_m[u]
+        for u in affected:
+            j = int(dist[u])
+            base = lbx[u] if dirty[u] else d[u]
+            lbx[u] = max(0, base - sum(C[:h - j + 1]))
+            lb[u] = max(structural(u), lbx[u])
+            dirty[u] = True
+        true_h = oracle.hdeg(g, h, alive).astype(np.int64)
+        true_m = oracle.hdeg(g, h - 1, alive).astype(np.int64)
+        for u in np.flatnonzero(alive):
+            assert d[u] >= true_h[u], (r, u)
+            assert dm[u] <= true_m[u], (r, u)
+            if dirty[u]:
+                assert lb[u] <= true_h[u], (r, u)
+        r += 1
+    return core, rnd
+
+
+@settings(max_examples=40, deadline=None)
+@given(kind=st.sampled_from(["er", "cl"]), n=st.integers(6, 45), h=st.integers(2, 4),
+       seed=st.integers(0, 10_000), lazy=st.booleans())
+def test_bounded_schedules_give_exact_cores(kind, n, h, seed, lazy):
+    """Schedules 1 and 3 remove exactly the vertices of the level-synchronous
+    peel (Algorithm 1's rounds), with every bound valid in every round."""
+    g = _graph(kind, n, seed)
+    core, rnd = _simulate_bounded(g, h, lazy)
+    c_ref, r_ref = oracle.peel(g, h)
+    assert (core == c_ref).all()
+    assert (rnd == r_ref).all()
+
+
+@pytest.mark.parametrize("lazy", [False, True])
+def test_bounded_schedules_closed_forms(lazy):
+    for h in (2, 3):
+        c, _ = _simulate_bounded(synth.cycle(2 * h + 5), h, lazy)
+        assert (c == 2 * h).all()
+        c, _ = _simulate_bounded(synth.complete(7), h, lazy)
+        assert (c == 6).all()
