@@ -12,6 +12,9 @@
   a proof: it tests (i) and (ii) on the sampled vertices only).
 * The plain schedule's affected sets: the sum over rounds of |A_r| and the
   round count equal the oracle's trace.
+* R-MAT scale 20 (ef 16), the benchmark's graph, in the benchmark's launch
+  configuration: h-degrees at h = 2, 3, 4 on sampled vertices equal the
+  oracle's, with and without an alive mask.
 """
 from concurrent.futures import ThreadPoolExecutor
 
@@ -67,6 +70,39 @@ def test_rmat16_hdeg_sampled(ctx, rmat16):
         d = _u32(ctx.hdeg(gr, h))
         ref, _ = oracle.hdeg_list(g, h, verts, threads=THREADS)
         assert (d[verts] == ref).all(), h
+    gr.close()
+
+
+def test_rmat20_hdeg_sampled_bench_launch(ctx):
+    """khdeg_compute over all of R-MAT scale 20 (ef 16, seed 1) with width 32
+    and 16 wavefronts per CU, as the benchmark times it: 256 random
+    vertices, the 16 highest-degree hubs and 16 isolated vertices match the
+    oracle bit for bit at h = 2, 3, 4, and at h = 3 under a random alive
+    mask (dead vertices 0)."""
+    import torch
+    from paper_2006_03372_amd import khcore
+    g = synth.rmat(20, 16, seed=1)
+    deg = g.degrees()
+    rng = np.random.default_rng(20)
+    hubs = np.argsort(deg, kind="stable")[-16:]
+    isolated = rng.choice(np.flatnonzero(deg == 0), 16, replace=False)
+    verts = np.unique(np.concatenate([rng.choice(g.n, 256, replace=False), hubs, isolated])).astype(np.uint32)
+    print(f"R-MAT-20 n={g.n} nnz={g.nnz}, {verts.size} sampled vertices", flush=True)
+    ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
+    ctx.set_option(khcore.OPT_WAVES_PER_CU, 16)
+    gr = ctx.graph(g)
+    for h in (2, 3, 4):
+        print(f"R-MAT-20 h={h}", flush=True)
+        d = _u32(ctx.hdeg(gr, h))
+        ref, _ = oracle.hdeg_list(g, h, verts, threads=THREADS)
+        assert (d[verts] == ref).all(), h
+        assert (d[isolated] == 0).all()
+    alive = synth.random_alive(g.n, 0.9, 21)
+    print("R-MAT-20 h=3 with an alive mask", flush=True)
+    d = _u32(ctx.hdeg(gr, 3, alive=torch.from_numpy(alive).cuda()))
+    ref, _ = oracle.hdeg_list(g, 3, verts, alive=alive, threads=THREADS)
+    assert (d[verts] == ref).all()
+    assert (d[alive == 0] == 0).all()
     gr.close()
 
 
