@@ -14,7 +14,9 @@
   round count equal the oracle's trace.
 * R-MAT scale 20 (ef 16), the benchmark's graph, in the benchmark's launch
   configuration: h-degrees at h = 2, 3, 4 on sampled vertices equal the
-  oracle's, with and without an alive mask.
+  oracle's, with and without an alive mask; the exact decomposition at
+  h = 4 (default schedule) passes the certificate on sampled vertices and
+  the hubs (a spot check).
 """
 from concurrent.futures import ThreadPoolExecutor
 
@@ -104,6 +106,33 @@ def test_rmat20_hdeg_sampled_bench_launch(ctx):
     assert (d[verts] == ref).all()
     assert (d[alive == 0] == 0).all()
     gr.close()
+
+
+def test_rmat20_h4_decomposition_certificate(ctx):
+    """The exact (k,4)-core decomposition of R-MAT scale 20 (ef 16, seed 1)
+    with the default schedule and host-driven rounds, width 32: conditions
+    (i) and (ii) of the peeling-order certificate hold on 200 random
+    vertices and the 16 highest-degree hubs, (iii) on every vertex."""
+    from paper_2006_03372_amd import khcore
+    g = synth.rmat(20, 16, seed=1)
+    deg = g.degrees()
+    rng = np.random.default_rng(22)
+    verts = np.unique(np.concatenate([rng.choice(g.n, 200, replace=False),
+                                      np.argsort(deg, kind="stable")[-16:]])).astype(np.uint32)
+    ctx.set_option(khcore.OPT_DRIVER, 0)
+    ctx.set_option(khcore.OPT_SCHEDULE, 3)
+    ctx.set_option(khcore.OPT_MAX_WIDTH, 32)
+    ctx.set_option(khcore.OPT_WAVES_PER_CU, 16)
+    gr = ctx.graph(g)
+    print(f"R-MAT-20 h=4 decomposition n={g.n} nnz={g.nnz}", flush=True)
+    c, r, st = ctx.core(gr, 4, with_round=True)
+    c, r = _u32(c), _u32(r)
+    gr.close()
+    ctx.set_option(khcore.OPT_SCHEDULE, 1)
+    print(f"rounds {st['rounds']}; certificate on {verts.size} vertices", flush=True)
+    fail = oracle.certificate(g, 4, c, r, verts, threads=THREADS)
+    assert fail.sum() == 0, fail
+    assert (c[deg == 0] == 0).all()
 
 
 @pytest.mark.parametrize("h", [2, 3, 4])
