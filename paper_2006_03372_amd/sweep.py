@@ -88,7 +88,7 @@ def schedules(ctx, g, desc, h, order=(1, 2, 0), driver=0):
                           "s": round(t, 3), "rounds": st["rounds"],
                           "local_rounds": st["local_rounds"], "h_recomputes": st["h_recomputes"],
                           "hm1_recomputes": st["hm1_recomputes"], "same": bool((c == ref).all())}), flush=True)
-    ctx.set_option(khcore.OPT_SCHEDULE, 1)
+    ctx.set_option(khcore.OPT_SCHEDULE, 3)  # the default
     gr.close()
 
 
